@@ -1,0 +1,270 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: each check uses a textbook
+routine (dense Gaussian elimination / eigendecomposition), a closed form, an
+identity that holds in exact arithmetic, or a brute-force construction.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import config1_cubic, random_sparse_symmetric, simple_cubic
+
+
+def _dense_solve(H, z, b):
+    A = H.to_dense()
+    return np.linalg.solve(z * np.eye(H.n) - A, b)
+
+
+@pytest.fixture(scope="module")
+def small():
+    rng = np.random.default_rng(7)
+    H = random_sparse_symmetric(36, 0.12, rng, diag_scale=1.5)
+    z = np.linspace(-3.0, 3.0, 9) + 1j * np.array([0.05, 0.2, 0.1, 0.3, 0.05, 0.5, 0.1, 0.2, 0.08])
+    return H, z
+
+
+def test_converged_solution_equals_dense_solve(small):
+    """Sec. 3.1 eq. lin_eq: x = (z - H)^{-1} b; dense Gaussian elimination is the definition."""
+    H, z = small
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=H.n) + 1j * rng.normal(size=H.n)
+    out = O.shifted_cocg(H, z, b, tol=1e-13, max_iter=2000)
+    assert out["ret"] == O.OK
+    for k in range(len(z)):
+        xd = _dense_solve(H, z[k], b)
+        assert np.linalg.norm(out["X"][k] - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+def test_fixed_iteration_matches_independent_cocg(small):
+    """Shift invariance of the Krylov space (Sec. 3.1 eq. inv_KS) and collinear residuals
+    (Sec. 3.3): after n steps the shifted iterate equals plain COCG on that shift."""
+    H, z = small
+    b = O.unit(H.n, 5) + 0.3 * O.unit(H.n, 11)
+    n_it = 12
+    out = O.shifted_cocg(H, z, b, fixed_iter=n_it, seed_index=2)
+    for k in range(len(z)):
+        ref = O.cocg(H, z[k], b, fixed_iter=n_it)
+        assert ref["iters"] == n_it
+        assert np.linalg.norm(out["X"][k] - ref["x"]) <= 1e-11 * np.linalg.norm(ref["x"])
+
+
+def test_collinear_residual(small):
+    """Sec. 3.3: the shifted residual b - (z_k - H) x_k equals the seed residual divided by pi_k."""
+    H, z = small
+    b = O.unit(H.n, 0)
+    A = H.to_dense()
+    for n_it in (1, 4, 9):
+        out = O.shifted_cocg(H, z, b, fixed_iter=n_it, seed_index=4)
+        for k in range(len(z)):
+            rk = b - (z[k] * np.eye(H.n) - A) @ out["X"][k]
+            assert np.linalg.norm(rk - out["r"] / out["pi"][k]) <= 1e-11 * np.linalg.norm(rk)
+
+
+def test_seed_choice_and_switch_point_do_not_change_iterates(small):
+    """Sec. 3.3 (seed switching keeps the computed information): the n-th iterate of every
+    shift is independent of the seed and of where the seed is switched."""
+    H, z = small
+    b = O.unit(H.n, 2)
+    n_it = 15
+    ref = O.shifted_cocg(H, z, b, fixed_iter=n_it, seed_index=0)["X"]
+    for seed, sw in ((3, None), (8, None), (0, (4, 6)), (5, (9, 1)), (1, (0, 7))):
+        X = O.shifted_cocg(H, z, b, fixed_iter=n_it, seed_index=seed, force_switch=sw)["X"]
+        for k in range(len(z)):
+            assert np.linalg.norm(X[k] - ref[k]) <= 1e-11 * np.linalg.norm(ref[k])
+
+
+def test_automatic_seed_switching_reaches_dense_solution():
+    """Seed switching in production mode: the seed converges first (large eta), the
+    others continue from a new seed and still reach the dense solution."""
+    rng = np.random.default_rng(11)
+    H = random_sparse_symmetric(48, 0.1, rng, diag_scale=2.0)
+    z = np.array([0.0 + 1.0j, -1.0 + 0.02j, 0.5 + 0.05j, 1.5 + 0.01j, -0.3 + 0.2j])
+    b = O.unit(H.n, 7)
+    out = O.shifted_cocg(H, z, b, tol=1e-12, max_iter=2000, seed_index=0)
+    assert out["ret"] == O.OK
+    assert len(out["switches"]) >= 1
+    for k in range(len(z)):
+        xd = _dense_solve(H, z[k], b)
+        assert np.linalg.norm(out["X"][k] - xd) <= 1e-9 * np.linalg.norm(xd)
+    # the switch target is the active shift with the largest recursive residual; all
+    # recorded iterations are increasing
+    its = [s[0] for s in out["switches"]]
+    assert its == sorted(its)
+
+
+def test_default_seed_rule(small):
+    H, z = small
+    # smallest Im z: indices 0 and 4 (0.05); tie broken by distance of Re z to Tr(H)/n
+    centre = np.trace(H.to_dense()) / H.n
+    cand = [0, 4]
+    expect = min(cand, key=lambda k: (abs(z[k].real - centre), k))
+    assert O.default_seed(H, z) == expect
+
+
+def test_error_bound_from_residual(small):
+    """Sec. 3.4: the residual norm bounds the error of G.  For real-symmetric H,
+    ||(z - H)^{-1}||_2 <= 1 / Im z, so |x - x*| <= ||b - (z - H) x|| / Im z."""
+    H, z = small
+    b = O.unit(H.n, 9)
+    out = O.shifted_cocg(H, z, b, tol=1e-4, max_iter=2000)
+    A = H.to_dense()
+    for k in range(len(z)):
+        xd = _dense_solve(H, z[k], b)
+        rt = np.linalg.norm(b - (z[k] * np.eye(H.n) - A) @ out["X"][k])
+        assert np.linalg.norm(out["X"][k] - xd) <= rt / z[k].imag * (1 + 1e-9)
+        # and the true residual agrees with the recursive one at this accuracy
+        assert rt <= 10 * max(out["res"][k], 1e-14)
+
+
+def test_closed_form_clean_cubic_lattice():
+    """Whole pipeline on a clean periodic L^3 lattice: G_00(z) = (1/L^3) sum_k 1/(z - e_k),
+    e_k = -2 sum_a cos k_a, k_a = 2 pi m / L (Bloch's theorem)."""
+    L = 8
+    H = simple_cubic(L, np.zeros(L ** 3))
+    z = np.linspace(-7, 7, 16) + 0.05j
+    out = O.shifted_cocg(H, z, O.unit(H.n, 0), tol=1e-11, max_iter=3000)
+    assert out["ret"] == O.OK
+    ka = 2 * np.pi * np.arange(L) / L
+    ek = (-2 * (np.cos(ka)[:, None, None] + np.cos(ka)[None, :, None] + np.cos(ka)[None, None, :])).ravel()
+    for k in range(len(z)):
+        g = np.mean(1.0 / (z[k] - ek))
+        assert abs(out["X"][k][0] - g) <= 1e-11 / z[k].imag * 10
+
+
+@pytest.mark.slow
+def test_closed_form_config1_size():
+    """Same closed form at the 16^3 size of the cubic workload (zero disorder, eta = 0.01)."""
+    p = config1_cubic(disorder=0.0)
+    out = O.shifted_cocg(p.H, p.z, O.unit(p.H.n, 0), tol=1e-10, max_iter=3000)
+    assert out["ret"] == O.OK
+    L = 16
+    ka = 2 * np.pi * np.arange(L) / L
+    ek = (-2 * (np.cos(ka)[:, None, None] + np.cos(ka)[None, :, None] + np.cos(ka)[None, None, :])).ravel()
+    for k in range(len(p.z)):
+        g = np.mean(1.0 / (p.z[k] - ek))
+        assert abs(out["X"][k][0] - g) <= 1e-10 / p.z[k].imag * 10
+
+
+def test_spectral_sum_rules():
+    """From Sec. 2.1.1 eqs. densityM/gf with f = 1: (1/2 pi i) closed-contour integrals
+    of G_jj, z G_jj and z^2 G_jj around the whole spectrum give 1, H_jj and (H^2)_jj."""
+    rng = np.random.default_rng(5)
+    H = random_sparse_symmetric(30, 0.15, rng)
+    lo, hi = O.gershgorin(H)
+    c, R = 0.5 * (lo + hi), 0.5 * (hi - lo) + 1.0
+    nq = 96
+    th = 2 * np.pi * (np.arange(nq) + 0.5) / nq
+    zq = c + R * np.exp(1j * th)
+    dz = R * np.exp(1j * th) / nq  # (1/2 pi i) dz on the trapezoid rule
+    A = H.to_dense()
+    A2 = A @ A
+    for j in (0, 13, 29):
+        out = O.shifted_cocg(H, zq, O.unit(H.n, j), tol=1e-13, max_iter=500)
+        g = out["X"][:, j]
+        assert abs(np.sum(dz * g) - 1.0) < 1e-10
+        assert abs(np.sum(dz * zq * g) - A[j, j]) < 1e-10
+        assert abs(np.sum(dz * zq ** 2 * g) - A2[j, j]) < 1e-9
+
+
+def _gapped_matrix(n, rng):
+    """Random sparse symmetric matrix whose spectrum has a clean gap around 0."""
+    H = random_sparse_symmetric(n, 0.1, rng)
+    A = H.to_dense()
+    w, V = np.linalg.eigh(A)
+    w = np.where(w < np.median(w), w - 1.0, w + 1.0)
+    return w, V
+
+
+def test_band_energy_and_density_matrix_match_eigendecomposition():
+    """Sec. 2.1.1: rho = sum_occ |phi><phi| (eq. densityM-1) equals the contour integral
+    of G (eq. densityM at T = 0), and E = Tr[rho H] = sum of occupied eigenvalues."""
+    from workloads import diamond
+
+    rng = np.random.default_rng(2)
+    H, _ = diamond(1, 1, 1, rng)
+    A = H.to_dense()
+    w, V = np.linalg.eigh(A)
+    mu = 0.5 * (w[15] + w[16])  # half filling, inside the gap between the two middle levels
+    # shift the Fermi level to 0 by moving the diagonal (keeps the CSR pattern)
+    from workloads import CSR
+
+    vals = H.val.copy()
+    rows = np.repeat(np.arange(H.n), np.diff(H.row_ptr))
+    vals[rows == H.col] -= mu
+    Hs = CSR(H.n, H.row_ptr, H.col, vals)
+    ws = w - mu
+    gap = min(abs(ws))
+    lo, _ = O.gershgorin(Hs)
+    zq, Wq = O.contour(lo - 1.0, 0.0, 128)
+    out = O.density_matrix_energy(Hs, zq, Wq, tol=1e-13, max_iter=2000)
+    E_exact = np.sum(ws[ws < 0])
+    assert gap > 0.05
+    assert abs(out["E"] - E_exact) < 1e-8 * max(1.0, abs(E_exact))
+    occ = V[:, ws < 0]
+    rho_d = occ @ occ.T
+    assert np.max(np.abs(out["rho"] - rho_d[rows, H.col])) < 1e-8
+    # E = Tr[rho H] over the stored entries
+    assert abs(np.sum(out["rho"] * Hs.val) - E_exact) < 1e-8 * max(1.0, abs(E_exact))
+
+
+def test_band_energy_gradient_dense_and_finite_difference():
+    """Derivative of the discrete band energy: dense (G^2)_ab and central differences."""
+    from workloads import CSR, diamond
+
+    rng = np.random.default_rng(4)
+    H, _ = diamond(1, 1, 1, rng)
+    lo, _ = O.gershgorin(H)
+    zq, Wq = O.contour(lo - 1.0, 0.0, 48)
+    # make sure no eigenvalue sits near the contour's real-axis end mu = 0
+    w = np.linalg.eigvalsh(H.to_dense())
+    assert np.min(np.abs(w)) > 0.02
+    out = O.density_matrix_energy(H, zq, Wq, tol=1e-13, max_iter=3000)
+    A = H.to_dense()
+    rows = np.repeat(np.arange(H.n), np.diff(H.row_ptr))
+    dense = np.zeros(H.nnz)
+    for zk, wk in zip(zq, Wq):
+        G = np.linalg.inv(zk * np.eye(H.n) - A)
+        dense += np.real(wk * zk * (G @ G)[rows, H.col])
+    assert np.max(np.abs(out["grad"] - dense)) < 1e-9 * max(1.0, np.max(np.abs(dense)))
+    # central finite differences on a symmetric pair (a, b) and on a diagonal entry
+    h = 1e-5
+    picks = [k for k in range(H.nnz) if rows[k] < H.col[k]][:3] + [k for k in range(H.nnz) if rows[k] == H.col[k]][:2]
+    for k in picks:
+        a, b = rows[k], H.col[k]
+        mirror = [m for m in range(H.nnz) if rows[m] == b and H.col[m] == a][0]
+        Es = []
+        for sgn in (+1, -1):
+            v = H.val.copy()
+            v[k] += sgn * h
+            if mirror != k:
+                v[mirror] += sgn * h
+            Es.append(O.density_matrix_energy(CSR(H.n, H.row_ptr, H.col, v), zq, Wq, tol=1e-13, max_iter=3000)["E"])
+        fd = (Es[0] - Es[1]) / (2 * h)
+        an = out["grad"][k] + (out["grad"][mirror] if mirror != k else 0.0)
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(an))
+
+
+def test_breakdown_is_reported():
+    """b.b = 0 (unconjugated) stops COCG at the first step; the oracle reports breakdown."""
+    rng = np.random.default_rng(0)
+    H = random_sparse_symmetric(20, 0.2, rng)
+    b = O.unit(20, 0) + 1j * O.unit(20, 1)
+    out = O.shifted_cocg(H, np.array([0.3 + 0.1j, 1.0 + 0.2j]), b)
+    assert out["ret"] == O.EBREAKDOWN
+    assert np.all(out["status"] == O.EBREAKDOWN)
+
+
+def test_non_convergence_is_reported(small):
+    H, z = small
+    out = O.shifted_cocg(H, z, O.unit(H.n, 1), tol=1e-12, max_iter=1)
+    assert out["ret"] == O.ENOCONV
+    assert np.all(out["iters"] == 1)
+
+
+def test_zero_rhs_gives_zero():
+    rng = np.random.default_rng(0)
+    H = random_sparse_symmetric(10, 0.3, rng)
+    out = O.shifted_cocg(H, np.array([0.1 + 0.1j]), np.zeros(10, dtype=complex))
+    assert out["ret"] == O.OK and np.all(out["X"] == 0)
