@@ -1,0 +1,186 @@
+/*
+ * scocg — shifted-COCG Green's-function solver for MI355X (gfx950), C ABI.
+ *
+ * The library solves, for a sparse real-symmetric Hamiltonian H (n x n),
+ *     (z_k 1 - H) x_{k,j} = b_j      for shifts k < n_shift, right-hand sides j < n_rhs
+ * (paper Sec. 3.1 eq. lin_eq, Sec. 3.3 eq. shift_lin_eq).  One seed shift per
+ * right-hand side is iterated with COCG, the method for complex-symmetric
+ * systems (Sec. 3.3); every other shift follows from the seed's scalars because
+ * the Krylov subspace is invariant under a scalar shift (Sec. 3.1 eq. inv_KS) and
+ * the shifted residuals stay collinear with the seed's (Sec. 3.3).  When the seed
+ * has converged the iteration continues from another shift, keeping the
+ * information computed so far (seed switching, Sec. 3.3).  Each (shift, rhs) pair
+ * stops when its residual norm ||b - (z - H) x|| / ||b|| is below the tolerance
+ * (Sec. 3.4 eq. residual).
+ *
+ * Conventions (every entry point):
+ *  - Complex numbers are interleaved (re, im) doubles, the memory layout of
+ *    complex128 / hipDoubleComplex.
+ *  - "device" pointers are HIP device memory owned by the caller; the library
+ *    never frees them and they must stay valid until the call returns.  "host"
+ *    pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Solver calls enqueue work on that stream and return after it has finished
+ *    (the iteration is steered from the host between blocks of iterations).
+ *  - Every call returns a status: SCOCG_OK, or one of the codes below; the
+ *    message of the last failure on the calling thread is scocg_last_error().
+ *    No C++ exception crosses the ABI.
+ *  - All computation runs on the GPU.  There is no CPU fallback.
+ */
+#ifndef SCOCG_H
+#define SCOCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SCOCG_OK = 0,
+    SCOCG_EINVAL = 1,     /* invalid argument or matrix */
+    SCOCG_ENOMEM = 2,     /* device allocation failed */
+    SCOCG_EHIP = 3,       /* HIP runtime error */
+    SCOCG_EBREAKDOWN = 4, /* COCG breakdown: r.r = 0, p.(Ap) = 0 or pi = 0 on an unconverged pair */
+    SCOCG_ENOCONV = 5     /* some pair did not reach the tolerance; results are still written */
+};
+
+typedef struct scocg_csr *scocg_csr_t;   /* uploaded Hamiltonian (library-owned) */
+typedef struct scocg_tape *scocg_tape_t; /* solutions kept for backward() (library-owned) */
+
+typedef struct {
+    double tol;             /* per-pair stop: ||r_k|| / ||b|| < tol (recursive residual) */
+    int32_t max_iter;       /* iteration limit per right-hand side */
+    int32_t precision;      /* 0: x_k, p_k stored in FP64; 1: stored and updated in FP32 */
+    int32_t seed_index;     /* initial seed shift; -1: smallest Im z, then Re z nearest Tr(H)/n, then lowest index */
+    int32_t seed_switching; /* 1: switch seed when it converges (Sec. 3.3) */
+    int32_t fixed_iter;     /* > 0: run exactly this many iterations, no freezing, no switching */
+    int32_t block;          /* iterations per deferred shift update (1,2,4,8,16); 0 = automatic */
+    int32_t shifts_per_wg;  /* shifts one workgroup updates in the deferred update; 0 = automatic */
+    int32_t check_true;     /* 1: compute the FP64 true residual of every pair into the report */
+    int32_t keep_tape;      /* 1: keep the solutions for backward() */
+    int32_t reserved[6];
+} scocg_opts;
+
+typedef struct {
+    int32_t iters;            /* iterations after which the pair was frozen (or the total) */
+    int32_t status;           /* SCOCG_OK (converged), SCOCG_ENOCONV or SCOCG_EBREAKDOWN */
+    double rel_res_recursive; /* ||r_seed|| / (|pi_k| ||b||) at exit */
+    double rel_res_true;      /* ||b - (z_k - H) x|| / ||b|| in FP64 (if check_true, else -1) */
+} scocg_pair_report;
+
+/* Fills *o with the defaults: tol 1e-8, max_iter 3000, FP64, default seed, switching on. */
+void scocg_default_opts(scocg_opts *o);
+
+/*
+ * Check a CSR matrix on the host: square, row_ptr monotone with row_ptr[0] = 0
+ * and row_ptr[n] = nnz, columns in range, sorted and unique in each row, values
+ * finite, and H exactly symmetric (H_ij == H_ji bitwise, the real-symmetric
+ * Hamiltonian of Sec. 2.1 / 2.2).  Host pointers.  Returns SCOCG_OK or SCOCG_EINVAL.
+ */
+int scocg_csr_validate(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t *col, const double *val);
+
+/*
+ * Upload H (host CSR arrays, int64 indices, FP64 values) to the current device.
+ * The library keeps its own device copy in a sliced-ELL layout (64-row slices,
+ * 32-bit columns) plus the CSR pattern; n and nnz must be below 2^31.
+ * validate = 1 runs scocg_csr_validate first.  On success *out owns the copy.
+ */
+int csr_upload(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t *col, const double *val, int validate,
+               void *stream, scocg_csr_t *out);
+
+/* Replace the values of H (same pattern, host array of nnz doubles, CSR order). */
+int csr_update_values(scocg_csr_t H, const double *val, void *stream);
+
+/* Dimension and stored-entry count of an uploaded matrix. */
+int64_t csr_n(scocg_csr_t H);
+int64_t csr_nnz(scocg_csr_t H);
+void csr_free(scocg_csr_t H);
+
+/*
+ * Solve (z_k 1 - H) X[j][k] = B[j] for all pairs (Sec. 3.3 eq. shift_lin_eq).
+ *   z    host, n_shift complex: the shifts (Im z may have either sign, not 0 on the spectrum)
+ *   B    device, [n_rhs][n] complex: right-hand sides
+ *   X    device, [n_rhs][n_shift][n] complex FP64 output (may be NULL only with keep_tape)
+ *   rep  host, [n_rhs][n_shift] reports, or NULL
+ *   tape if non-NULL and o->keep_tape, receives the solutions for backward()
+ * Returns SCOCG_OK, SCOCG_ENOCONV (results written, see rep), SCOCG_EBREAKDOWN,
+ * SCOCG_EINVAL, SCOCG_ENOMEM or SCOCG_EHIP.
+ */
+int shifted_cocg_solve(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const double *B,
+                       const scocg_opts *o, double *X, scocg_pair_report *rep, scocg_tape_t *tape, void *stream);
+
+/*
+ * Diagonal Green's function G_jj(z_k) = [(z_k - H)^{-1}]_jj (Sec. 2.1.1 eq. gf)
+ * for the unit right-hand sides e_j, j = rhs_idx[c].
+ *   rhs_idx host, n_rhs indices in [0, n)
+ *   G       device, [n_shift][n_rhs] complex output
+ * Only the diagonal entries of the solutions are kept (the p_k vectors are still
+ * full length, which seed switching needs), unless o->keep_tape asks for the
+ * full solutions.
+ */
+int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,
+                const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream);
+
+/*
+ * Density matrix and band energy at zero temperature from a contour integral of
+ * G (Sec. 2.1.1 eq. densityM, with <X> = Tr[rho X] and X = H):
+ *     rho_ab = Re sum_q w_q G_ab(z_q),     E = Re sum_q w_q z_q sum_j G_jj(z_q)
+ * for the columns j in rhs_idx (all n columns give the full rho on H's pattern
+ * and the full band energy).  z, w: host, n_quad complex nodes and weights (see
+ * scocg_contour).  Outputs (device, accumulated into, so zero them first):
+ *   rho_nnz [nnz] or NULL: rho on the stored entries of H, CSR order (column j's entries)
+ *   E_band  [1]          : band energy contribution of the columns
+ *   dE_dval [nnz] or NULL: derivative of E with respect to each stored entry,
+ *                          Re sum_q w_q z_q sum_j x_qj[a] x_qj[b]
+ * Right-hand sides are processed in batches of at most rhs_batch (0 = automatic).
+ */
+int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double *z, const double *w, int64_t n_rhs,
+                          const int64_t *rhs_idx, const scocg_opts *o, int64_t rhs_batch, double *rho_nnz,
+                          double *E_band, double *dE_dval, void *stream);
+
+/*
+ * Gradient of a real loss L through G = greens_diag(...) or X = shifted_cocg_solve(...)
+ * with respect to the stored entries of H.  Because z - H is complex symmetric,
+ * dG_jj/dH_ab = x_j[a] x_j[b] and no second solve is needed:
+ *     dL/dH_ab = Re sum_{k,j} conj(g_kj) x_kj[a] x_kj[b]
+ * with g = dL/dRe G + i dL/dIm G (PyTorch's convention for complex tensors).
+ *   grad_G   device, [n_shift][n_rhs] complex (greens_diag tape only)
+ *   grad_val device, [nnz] FP64, accumulated into (per stored CSR entry)
+ */
+int backward(scocg_tape_t tape, const double *grad_G, double *grad_val, void *stream);
+void tape_free(scocg_tape_t t);
+
+/*
+ * Nodes and weights of the zero-temperature contour: the upper half of the circle
+ * through e_lo and mu, Gauss-Legendre in the angle, folded with the mirror
+ * symmetry G(conj z) = conj G(z) so that rho = Re sum_q w_q G(z_q).  Host
+ * arrays of 2*n_quad doubles.
+ */
+int scocg_contour(double e_lo, double mu, int64_t n_quad, double *z, double *w);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *scocg_last_error(void);
+
+/*
+ * Timing of the most recent solve on this thread, from HIP events on its stream:
+ * the summed duration and launch count of the deferred shift-update kernel and
+ * of the seed kernels, and the algorithmic bytes the shift update moved.
+ */
+typedef struct {
+    double update_ms;       /* total time in the deferred per-shift update kernel */
+    int64_t update_launches;
+    double update_bytes;    /* algorithmic bytes of those launches */
+    double total_ms;        /* wall time of the solve on the stream */
+    int64_t iterations;     /* seed iterations summed over right-hand sides */
+    int64_t blocks;         /* blocks of iterations */
+    int64_t switches;       /* seed switches */
+} scocg_timing;
+int scocg_last_timing(scocg_timing *t);
+/* 1: record per-launch events around the update kernel (adds a small overhead). */
+void scocg_set_profiling(int on);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

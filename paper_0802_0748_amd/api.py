@@ -1,0 +1,233 @@
+"""PyTorch-facing binding of the shifted-COCG library.
+
+PyTorch provides device memory and the stream; every computation runs in
+libscocg.so (HIP kernels for gfx950).  Function names follow the C ABI.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _capi as C
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("the shifted-COCG library needs a HIP device; none is visible")
+
+
+def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switching=True, fixed_iter=0, block=0,
+            shifts_per_wg=0, check_true=False, keep_tape=False) -> C.Opts:
+    o = C.Opts()
+    C.load().scocg_default_opts(ctypes.byref(o))
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.precision = {"fp64": 0, "fp32": 1, 0: 0, 1: 1}[precision]
+    o.seed_index = int(seed_index)
+    o.seed_switching = int(bool(seed_switching))
+    o.fixed_iter = int(fixed_iter)
+    o.block = int(block)
+    o.shifts_per_wg = int(shifts_per_wg)
+    o.check_true = int(bool(check_true))
+    o.keep_tape = int(bool(keep_tape))
+    return o
+
+
+def csr_validate(row_ptr, col, val) -> None:
+    """Host-side check of a CSR matrix (shape, ordering, finiteness, exact symmetry)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col, dtype=np.int64)
+    v = np.ascontiguousarray(val, dtype=np.float64)
+    n = len(rp) - 1
+    C.check(C.load().scocg_csr_validate(n, len(ci), rp.ctypes.data, ci.ctypes.data, v.ctypes.data))
+
+
+class Hamiltonian:
+    """A real-symmetric sparse H uploaded to the current device (csr_upload)."""
+
+    def __init__(self, row_ptr, col, val, validate=True):
+        _require_gpu()
+        lib = C.load()
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col, dtype=np.int64)
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        self.n = len(rp) - 1
+        self.nnz = len(ci)
+        self.row_ptr, self.col = rp, ci
+        h = ctypes.c_void_p()
+        C.check(lib.csr_upload(self.n, self.nnz, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, int(validate),
+                               _stream_ptr(), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_csr(cls, H, validate=True):
+        return cls(H.row_ptr, H.col, H.val, validate=validate)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def update_values(self, val):
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        if len(v) != self.nnz:
+            raise ValueError("value array has the wrong length")
+        C.check(C.load().csr_update_values(self._h, v.ctypes.data, _stream_ptr()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            C.load().csr_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tape:
+    """Solutions kept by a solve for backward()."""
+
+    def __init__(self, h, kind, n_shift, n_rhs, nnz):
+        self._h = h
+        self.kind = kind
+        self.nnz = nnz
+        self.n_shift = n_shift
+        self.n_rhs = n_rhs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            C.load().tape_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _z_host(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    return z, z.ctypes.data
+
+
+def _report(rep, n_rhs, n_shift):
+    a = np.ctypeslib.as_array(rep, shape=(n_rhs * n_shift,))
+    return dict(iters=np.array(a["iters"]).reshape(n_rhs, n_shift),
+                status=np.array(a["status"]).reshape(n_rhs, n_shift),
+                res=np.array(a["rel_res_recursive"]).reshape(n_rhs, n_shift),
+                res_true=np.array(a["rel_res_true"]).reshape(n_rhs, n_shift))
+
+
+def last_timing() -> dict:
+    t = C.Timing()
+    C.load().scocg_last_timing(ctypes.byref(t))
+    return {f: getattr(t, f) for f, _ in C.Timing._fields_}
+
+
+def set_profiling(on: bool) -> None:
+    C.load().scocg_set_profiling(int(bool(on)))
+
+
+def _allowed(allow_noconv, allow_breakdown):
+    a = [C.OK]
+    if allow_noconv:
+        a.append(C.ENOCONV)
+    if allow_breakdown:
+        a.append(C.EBREAKDOWN)
+    return tuple(a)
+
+
+def shifted_cocg_solve(H: Hamiltonian, z, B: torch.Tensor, out: torch.Tensor = None, allow_noconv=True,
+                       allow_breakdown=False, **opts):
+    """Solve (z_k - H) X[j, k] = B[j] for every shift k and right-hand side j.
+
+    B is a complex128 device tensor [n_rhs, n].  Returns (X [n_rhs, n_shift, n],
+    report dict, tape or None, status code).
+    """
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    if B.dtype != torch.complex128 or not B.is_cuda or B.dim() != 2 or B.shape[1] != H.n:
+        raise ValueError("B must be a complex128 device tensor of shape [n_rhs, n]")
+    B = B.contiguous()
+    K, M = B.shape[0], len(zh)
+    if out is None:
+        out = torch.empty((K, M, H.n), dtype=torch.complex128, device=B.device)
+    o = options(**opts)
+    rep = (C.PairReport * (K * M))()
+    tape = ctypes.c_void_p()
+    rc = lib.shifted_cocg_solve(H.handle, M, zp, K, B.data_ptr(), ctypes.byref(o), out.data_ptr(), rep,
+                                ctypes.byref(tape) if o.keep_tape else None, _stream_ptr())
+    C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
+    t = Tape(tape, "solve", M, K, H.nnz) if o.keep_tape and tape.value else None
+    return out, _report(rep, K, M), t, rc
+
+
+def greens_diag(H: Hamiltonian, z, rhs_idx, allow_noconv=True, allow_breakdown=False, device=None, **opts):
+    """G_jj(z_k) for unit right-hand sides e_j (j in rhs_idx); returns (G [n_shift, n_rhs], report, tape, rc)."""
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    idx = np.ascontiguousarray(rhs_idx, dtype=np.int64)
+    K, M = len(idx), len(zh)
+    G = torch.empty((M, K), dtype=torch.complex128, device=device or torch.device("cuda"))
+    o = options(**opts)
+    rep = (C.PairReport * (K * M))()
+    tape = ctypes.c_void_p()
+    rc = lib.greens_diag(H.handle, M, zp, K, idx.ctypes.data, ctypes.byref(o), G.data_ptr(), rep,
+                         ctypes.byref(tape) if o.keep_tape else None, _stream_ptr())
+    C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
+    t = Tape(tape, "greens", M, K, H.nnz) if o.keep_tape and tape.value else None
+    return G, _report(rep, K, M), t, rc
+
+
+def contour(e_lo: float, mu: float, n_quad: int):
+    """Zero-temperature contour nodes z_q and weights w_q (rho = Re sum_q w_q G(z_q))."""
+    z = np.zeros(n_quad, dtype=np.complex128)
+    w = np.zeros(n_quad, dtype=np.complex128)
+    C.check(C.load().scocg_contour(float(e_lo), float(mu), int(n_quad), z.ctypes.data, w.ctypes.data))
+    return z, w
+
+
+def density_matrix_energy(H: Hamiltonian, z, w, rhs_idx=None, want_rho=True, want_grad=False, rhs_batch=0,
+                          allow_noconv=True, **opts):
+    """rho on H's stored entries, band energy E and dE/dH_ab for the columns in rhs_idx."""
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    wh, wp = _z_host(w)
+    if len(wh) != len(zh):
+        raise ValueError("z and w must have the same length")
+    idx = np.ascontiguousarray(np.arange(H.n) if rhs_idx is None else rhs_idx, dtype=np.int64)
+    dev = torch.device("cuda")
+    rho = torch.zeros(H.nnz, dtype=torch.float64, device=dev) if want_rho else None
+    grad = torch.zeros(H.nnz, dtype=torch.float64, device=dev) if want_grad else None
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    o = options(**opts)
+    rc = lib.density_matrix_energy(H.handle, len(zh), zp, wp, len(idx), idx.ctypes.data, ctypes.byref(o),
+                                   int(rhs_batch), rho.data_ptr() if rho is not None else None, E.data_ptr(),
+                                   grad.data_ptr() if grad is not None else None, _stream_ptr())
+    C.check(rc, allow=(C.OK, C.ENOCONV) if allow_noconv else (C.OK,))
+    return dict(rho=rho, E=E, grad=grad, rc=rc)
+
+
+def backward(tape: Tape, grad_G: torch.Tensor, grad_val: torch.Tensor = None) -> torch.Tensor:
+    """dL/dH per stored CSR entry from dL/dG ([n_shift, n_rhs] complex128, PyTorch's convention
+    g = dL/dRe G + i dL/dIm G).  Accumulates into grad_val if given."""
+    _require_gpu()
+    if tape is None or tape._h is None:
+        raise ValueError("no tape")
+    g = grad_G.to(torch.complex128).contiguous()
+    if tuple(g.shape) != (tape.n_shift, tape.n_rhs):
+        raise ValueError("grad_G must have shape [n_shift, n_rhs]")
+    if grad_val is None:
+        grad_val = torch.zeros(tape.nnz, dtype=torch.float64, device=g.device)
+    C.check(C.load().backward(tape._h, g.data_ptr(), grad_val.data_ptr(), _stream_ptr()))
+    return grad_val

@@ -1,0 +1,767 @@
+// Host side of libscocg: argument checking, matrix upload, the iteration driver and the
+// observable entry points declared in include/scocg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/scocg.h"
+#include "scocg_internal.h"
+
+using namespace scocg;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local scocg_timing g_timing = {};
+int g_profiling = 0;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(SCOCG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device allocations released when the owner goes out of scope.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t b)
+    {
+        release();
+        bytes = b;
+        if (b == 0) return hipSuccess;
+        return hipMalloc(&ptr, b);
+    }
+    template <typename T>
+    T *as() const { return (T *)ptr; }
+};
+
+struct PinnedBuf {
+    void *ptr = nullptr;
+    ~PinnedBuf()
+    {
+        if (ptr) (void)hipHostFree(ptr);
+    }
+    hipError_t alloc(size_t b) { return hipHostMalloc(&ptr, b, hipHostMallocDefault); }
+};
+
+}  // namespace
+
+struct scocg_csr {
+    DevCSR d;
+    std::vector<int64_t> h_row_ptr, h_col, h_ell_src;
+    std::vector<double> h_val;
+};
+
+struct scocg_tape {
+    scocg_csr *H = nullptr;
+    int64_t K = 0, M = 0, n = 0;
+    DevBuf X;  // [K][M][n] complex FP64
+};
+
+// ------------------------------------------------------------------------------------------
+// matrix checks and upload
+// ------------------------------------------------------------------------------------------
+extern "C" int scocg_csr_validate(int64_t n, int64_t nnz, const int64_t *rp, const int64_t *col, const double *val)
+{
+    if (n <= 0) return fail(SCOCG_EINVAL, "n must be positive");
+    if (nnz < 0) return fail(SCOCG_EINVAL, "nnz must be non-negative");
+    if (!rp || (nnz > 0 && (!col || !val))) return fail(SCOCG_EINVAL, "null CSR array");
+    if (rp[0] != 0 || rp[n] != nnz) return fail(SCOCG_EINVAL, "row_ptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return fail(SCOCG_EINVAL, "row_ptr is not monotone at row " + std::to_string(i));
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (col[k] < 0 || col[k] >= n)
+                return fail(SCOCG_EINVAL, "column out of range in row " + std::to_string(i));
+            if (k > rp[i] && col[k] <= col[k - 1])
+                return fail(SCOCG_EINVAL, "columns not sorted/unique in row " + std::to_string(i));
+            if (!std::isfinite(val[k])) return fail(SCOCG_EINVAL, "non-finite value in row " + std::to_string(i));
+        }
+    }
+    // symmetry: H_ij must equal H_ji bitwise (binary search in row j)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t j = col[k];
+            const int64_t *b = col + rp[j], *e = col + rp[j + 1];
+            const int64_t *f = std::lower_bound(b, e, i);
+            if (f == e || *f != i)
+                return fail(SCOCG_EINVAL, "pattern not symmetric at (" + std::to_string(i) + "," + std::to_string(j) + ")");
+            if (val[f - col] != val[k])
+                return fail(SCOCG_EINVAL, "values not symmetric at (" + std::to_string(i) + "," + std::to_string(j) + ")");
+        }
+    }
+    return SCOCG_OK;
+}
+
+static void free_dev(DevCSR &d)
+{
+    void *ptrs[] = {d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.d_ell_pos, d.d_row_ptr, d.d_col, d.d_val};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    std::memset(&d, 0, sizeof(d));
+}
+
+template <typename T>
+static hipError_t upload(T **dst, const T *src, size_t count, hipStream_t st)
+{
+    hipError_t e = hipMalloc((void **)dst, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (count == 0) return hipSuccess;
+    e = hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+extern "C" int csr_upload(int64_t n, int64_t nnz, const int64_t *rp, const int64_t *col, const double *val,
+                          int validate, void *stream, scocg_csr_t *out)
+{
+    g_err.clear();
+    if (!out) return fail(SCOCG_EINVAL, "out is null");
+    *out = nullptr;
+    if (n <= 0 || n >= (1LL << 31) || nnz < 0 || nnz >= (1LL << 31))
+        return fail(SCOCG_EINVAL, "n and nnz must be in (0, 2^31)");
+    if (!rp || (nnz > 0 && (!col || !val))) return fail(SCOCG_EINVAL, "null CSR array");
+    if (validate) {
+        int rc = scocg_csr_validate(n, nnz, rp, col, val);
+        if (rc) return rc;
+    } else if (rp[0] != 0 || rp[n] != nnz) {
+        return fail(SCOCG_EINVAL, "row_ptr must start at 0 and end at nnz");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    scocg_csr *H = new scocg_csr();
+    DevCSR &d = H->d;
+    d.n = n;
+    d.nnz = nnz;
+    d.nslices = (n + 63) / 64;
+    H->h_row_ptr.assign(rp, rp + n + 1);
+    H->h_col.assign(col, col + nnz);
+    H->h_val.assign(val, val + nnz);
+    // 64-row slices, padded to the widest row of the slice; padding points at row 0 with value 0
+    std::vector<int64_t> sptr(d.nslices + 1, 0);
+    std::vector<int32_t> sw(d.nslices, 0);
+    int maxw = 0;
+    for (int64_t s = 0; s < d.nslices; ++s) {
+        int w = 0;
+        for (int64_t r = s * 64; r < std::min(n, s * 64 + 64); ++r) w = std::max<int>(w, (int)(rp[r + 1] - rp[r]));
+        sw[s] = w;
+        maxw = std::max(maxw, w);
+        sptr[s + 1] = sptr[s] + (int64_t)w * 64;
+    }
+    d.ell_nnz = sptr[d.nslices];
+    d.max_w = maxw;
+    std::vector<int32_t> ecol(d.ell_nnz, 0);
+    std::vector<double> eval(d.ell_nnz, 0.0);
+    H->h_ell_src.assign(d.ell_nnz, -1);
+    for (int64_t s = 0; s < d.nslices; ++s) {
+        for (int lane = 0; lane < 64; ++lane) {
+            const int64_t r = s * 64 + lane;
+            if (r >= n) continue;
+            for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+                const int64_t slot = sptr[s] + (k - rp[r]) * 64 + lane;
+                ecol[slot] = (int32_t)col[k];
+                eval[slot] = val[k];
+                H->h_ell_src[slot] = k;
+            }
+        }
+    }
+    double tr = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (col[k] == i) tr += val[k];
+    d.trace = tr;
+    std::vector<int32_t> col32(nnz);
+    for (int64_t k = 0; k < nnz; ++k) col32[k] = (int32_t)col[k];
+    hipError_t e = hipSuccess;
+    if ((e = upload(&d.d_slice_ptr, sptr.data(), sptr.size(), st)) != hipSuccess ||
+        (e = upload(&d.d_slice_w, sw.data(), sw.size(), st)) != hipSuccess ||
+        (e = upload(&d.d_ell_col, ecol.data(), ecol.size(), st)) != hipSuccess ||
+        (e = upload(&d.d_ell_val, eval.data(), eval.size(), st)) != hipSuccess ||
+        (e = upload(&d.d_row_ptr, rp, (size_t)n + 1, st)) != hipSuccess ||
+        (e = upload(&d.d_col, col32.data(), col32.size(), st)) != hipSuccess ||
+        (e = upload(&d.d_val, val, (size_t)nnz, st)) != hipSuccess) {
+        free_dev(d);
+        delete H;
+        return fail(e == hipErrorOutOfMemory ? SCOCG_ENOMEM : SCOCG_EHIP,
+                    std::string("csr_upload: ") + hipGetErrorString(e));
+    }
+    *out = H;
+    return SCOCG_OK;
+}
+
+extern "C" int csr_update_values(scocg_csr_t H, const double *val, void *stream)
+{
+    g_err.clear();
+    if (!H || !val) return fail(SCOCG_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    DevCSR &d = H->d;
+    std::vector<double> eval(d.ell_nnz, 0.0);
+    for (int64_t s = 0; s < d.ell_nnz; ++s)
+        if (H->h_ell_src[s] >= 0) eval[s] = val[H->h_ell_src[s]];
+    H->h_val.assign(val, val + d.nnz);
+    double tr = 0;
+    for (int64_t i = 0; i < d.n; ++i)
+        for (int64_t k = H->h_row_ptr[i]; k < H->h_row_ptr[i + 1]; ++k)
+            if (H->h_col[k] == i) tr += val[k];
+    d.trace = tr;
+    HIPCHK(hipMemcpyAsync(d.d_ell_val, eval.data(), eval.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.d_val, val, d.nnz * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SCOCG_OK;
+}
+
+extern "C" int64_t csr_n(scocg_csr_t H) { return H ? H->d.n : -1; }
+extern "C" int64_t csr_nnz(scocg_csr_t H) { return H ? H->d.nnz : -1; }
+
+extern "C" void csr_free(scocg_csr_t H)
+{
+    if (!H) return;
+    free_dev(H->d);
+    delete H;
+}
+
+extern "C" void scocg_default_opts(scocg_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->max_iter = 3000;
+    o->precision = 0;
+    o->seed_index = -1;
+    o->seed_switching = 1;
+    o->fixed_iter = 0;
+    o->block = 0;
+    o->shifts_per_wg = 0;
+    o->check_true = 0;
+    o->keep_tape = 0;
+}
+
+extern "C" const char *scocg_last_error(void) { return g_err.c_str(); }
+
+extern "C" int scocg_last_timing(scocg_timing *t)
+{
+    if (!t) return SCOCG_EINVAL;
+    *t = g_timing;
+    return SCOCG_OK;
+}
+
+extern "C" void scocg_set_profiling(int on) { g_profiling = on ? 1 : 0; }
+
+// ------------------------------------------------------------------------------------------
+// the solver driver
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// Initial seed: smallest Im z; ties by |Re z - Tr(H)/n|; then lowest index.
+int default_seed(const double *z, int64_t M, double centre)
+{
+    int best = 0;
+    for (int64_t k = 1; k < M; ++k) {
+        const double ik = z[2 * k + 1], ib = z[2 * best + 1];
+        const double dk = std::fabs(z[2 * k] - centre), db = std::fabs(z[2 * best] - centre);
+        if (ik < ib || (ik == ib && dk < db)) best = (int)k;
+    }
+    return best;
+}
+
+struct SolveRequest {
+    scocg_csr *H;
+    int64_t M, K;
+    const double *z;          // host [M] complex
+    const double2 *B;         // device [K][n] or null (unit vectors)
+    const int64_t *unit_idx;  // host [K] (unit vectors) or null
+    scocg_opts o;
+    double2 *Xout;            // device FP64 [K][M][n] or null
+    bool projection;          // keep only x at row unit_idx[j]
+    double2 *Gout;            // device [M][K] or null
+    scocg_pair_report *rep;
+    DevBuf *keepX;            // receives the full FP64 solutions (tape) or null
+};
+
+int solve(SolveRequest &rq, hipStream_t st)
+{
+    scocg_csr *Hh = rq.H;
+    const DevCSR &H = Hh->d;
+    const int64_t n = H.n, K = rq.K, M = rq.M;
+    const scocg_opts &o = rq.o;
+    if (M <= 0 || K <= 0) return fail(SCOCG_EINVAL, "n_shift and n_rhs must be positive");
+    if (M > (1 << 20) || K > 65535) return fail(SCOCG_EINVAL, "too many shifts or right-hand sides");
+    if (!(o.tol > 0) && o.fixed_iter <= 0) return fail(SCOCG_EINVAL, "tol must be positive");
+    if (o.max_iter <= 0 && o.fixed_iter <= 0) return fail(SCOCG_EINVAL, "max_iter must be positive");
+    if (o.precision != 0 && o.precision != 1) return fail(SCOCG_EINVAL, "precision must be 0 or 1");
+    for (int64_t k = 0; k < M; ++k)
+        if (!std::isfinite(rq.z[2 * k]) || !std::isfinite(rq.z[2 * k + 1]))
+            return fail(SCOCG_EINVAL, "non-finite shift");
+    int TB = o.block > 0 ? o.block : 8;
+    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16)
+        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8 or 16");
+    int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 32);
+    int seed0;
+    if (o.seed_index >= 0) {
+        if (o.seed_index >= M) return fail(SCOCG_EINVAL, "seed_index out of range");
+        seed0 = o.seed_index;
+    } else {
+        seed0 = default_seed(rq.z, M, H.trace / (double)n);
+    }
+    const bool fixed = o.fixed_iter > 0;
+    const int32_t limit = fixed ? o.fixed_iter : o.max_iter;
+    const bool need_full = !rq.projection;
+    const size_t KM = (size_t)K * M;
+    const size_t vec = (size_t)K * n;
+    const size_t esz = o.precision == 0 ? sizeof(double2) : sizeof(float2);
+
+    g_timing = scocg_timing{};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    HIPCHK(hipEventCreate(&ev_t0));
+    HIPCHK(hipEventCreate(&ev_t1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } evg{ev_t0, ev_t1};
+    HIPCHK(hipEventRecord(ev_t0, st));
+
+    SolveDev s{};
+    s.n = n;
+    s.K = K;
+    s.M = M;
+    s.TB = TB;
+    s.precision = o.precision;
+    s.fixed = fixed ? 1 : 0;
+    s.switching = o.seed_switching ? 1 : 0;
+    s.tol = o.tol;
+    s.nblk = (n + 255) / 256;
+    s.shifts_per_wg = G;
+
+    DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
+        brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats;
+    auto A = [&](DevBuf &b, size_t bytes) -> hipError_t { return b.alloc(bytes); };
+    hipError_t e = hipSuccess;
+#define ALLOC(buf, bytes)                                                                                  \
+    do {                                                                                                   \
+        e = A(buf, bytes);                                                                                 \
+        if (e != hipSuccess)                                                                               \
+            return fail(SCOCG_ENOMEM, std::string("device allocation of ") + std::to_string((size_t)(bytes)) + \
+                                          " bytes failed: " + hipGetErrorString(e));                      \
+    } while (0)
+    ALLOC(bz, M * sizeof(double2));
+    ALLOC(bseed, K * sizeof(SeedState));
+    ALLOC(bring, (size_t)(TB + 1) * vec * sizeof(double2));
+    ALLOC(bp, vec * sizeof(double2));
+    ALLOC(bq, vec * sizeof(double2));
+    ALLOC(bP, KM * n * esz);
+    const bool x_is_out = need_full && o.precision == 0 && rq.Xout && !rq.keepX;
+    if (need_full && !x_is_out) ALLOC(bX, KM * n * esz);
+    if (!need_full) {
+        ALLOC(bXproj, KM * sizeof(double2));
+        ALLOC(bprow, K * sizeof(int64_t));
+    }
+    ALLOC(bpi, KM * sizeof(double2));
+    ALLOC(bpip, KM * sizeof(double2));
+    ALLOC(bbk, KM * sizeof(double2));
+    ALLOC(bres, KM * sizeof(double));
+    ALLOC(biters, KM * sizeof(int32_t));
+    ALLOC(bpst, KM * sizeof(int32_t));
+    ALLOC(bact, KM * sizeof(int32_t));
+    ALLOC(bnact, KM * sizeof(int32_t));
+    ALLOC(bah, K * TB * sizeof(double2));
+    ALLOC(bbh, K * TB * sizeof(double2));
+    ALLOC(brn, K * TB * sizeof(double));
+    ALLOC(bcoef, KM * TB * 3 * sizeof(double2));
+    ALLOC(bp2, K * s.nblk * sizeof(double2));
+    ALLOC(bp1, K * s.nblk * sizeof(double));
+    ALLOC(bcnt, K * sizeof(uint32_t));
+    ALLOC(bsd, K * sizeof(int32_t));
+    ALLOC(bstats, 2 * sizeof(unsigned long long));
+    if (rq.unit_idx) ALLOC(bidx, K * sizeof(int64_t));
+
+    s.z = bz.as<double2>();
+    s.seed = bseed.as<SeedState>();
+    s.ring = bring.as<double2>();
+    s.p = bp.as<double2>();
+    s.q = bq.as<double2>();
+    s.P = bP.ptr;
+    s.X = need_full ? (x_is_out ? (void *)rq.Xout : bX.ptr) : nullptr;
+    s.Xproj = need_full ? nullptr : bXproj.as<double2>();
+    s.proj_row = need_full ? nullptr : bprow.as<int64_t>();
+    s.pi = bpi.as<double2>();
+    s.pi_prev = bpip.as<double2>();
+    s.beta_k = bbk.as<double2>();
+    s.res = bres.as<double>();
+    s.iters = biters.as<int32_t>();
+    s.pstatus = bpst.as<int32_t>();
+    s.active = bact.as<int32_t>();
+    s.nact = bnact.as<int32_t>();
+    s.ahist = bah.as<double2>();
+    s.bhist = bbh.as<double2>();
+    s.rnhist = brn.as<double>();
+    s.coef = bcoef.as<double2>();
+    s.part2 = bp2.as<double2>();
+    s.part1 = bp1.as<double>();
+    s.cnt = bcnt.as<uint32_t>();
+    s.stats = bstats.as<unsigned long long>();
+
+    std::vector<int32_t> seeds(K, seed0);
+    HIPCHK(hipMemcpyAsync(bz.ptr, rq.z, M * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bsd.ptr, seeds.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (rq.unit_idx) {
+        HIPCHK(hipMemcpyAsync(bidx.ptr, rq.unit_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        if (!need_full) HIPCHK(hipMemcpyAsync(bprow.ptr, rq.unit_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(launch_zero(bcnt.ptr, K * sizeof(uint32_t), st));
+    HIPCHK(launch_zero(bstats.ptr, 2 * sizeof(unsigned long long), st));
+    if (need_full) HIPCHK(launch_zero(s.X, KM * n * esz, st));
+    HIPCHK(launch_init(s, H, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, bsd.as<int32_t>(), limit, st));
+
+    PinnedBuf host_state;
+    HIPCHK(host_state.alloc(K * sizeof(SeedState)));
+    SeedState *hs = (SeedState *)host_state.ptr;
+
+    std::vector<hipEvent_t> evs;
+    struct EvList {
+        std::vector<hipEvent_t> *v;
+        ~EvList()
+        {
+            for (auto e : *v) (void)hipEventDestroy(e);
+        }
+    } evl{&evs};
+    hipEvent_t fe0 = nullptr, fe1 = nullptr;
+    if (g_profiling) {
+        HIPCHK(hipEventCreate(&fe0));
+        HIPCHK(hipEventCreate(&fe1));
+        evs.push_back(fe0);
+        evs.push_back(fe1);
+    }
+
+    // worst case: every block advances one rhs by >= 1 iteration or finishes / switches one rhs
+    const int64_t max_blocks = (int64_t)K * ((int64_t)limit + 2 * M + 4) + 8;
+    int64_t blocks = 0;
+    bool done = false;
+    while (!done) {
+        for (int t = 0; t < TB; ++t) {
+            HIPCHK(launch_p_update(s, st));
+            HIPCHK(launch_spmv(s, H, st));
+            HIPCHK(launch_r_update(s, st));
+        }
+        HIPCHK(launch_pair_scalars(s, st));
+        if (g_profiling) HIPCHK(hipEventRecord(fe0, st));
+        HIPCHK(launch_flush(s, st));
+        if (g_profiling) HIPCHK(hipEventRecord(fe1, st));
+        HIPCHK(launch_block_finalize(s, st));
+        HIPCHK(launch_switch_vectors(s, st));
+        HIPCHK(hipMemcpyAsync(hs, s.seed, K * sizeof(SeedState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ++blocks;
+        if (g_profiling) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, fe0, fe1));
+            g_timing.update_ms += ms;
+            g_timing.update_launches += 1;
+        }
+        done = true;
+        for (int64_t j = 0; j < K; ++j)
+            if (hs[j].status != SEED_STOPPED) done = false;
+        if (blocks > max_blocks) return fail(SCOCG_EHIP, "iteration driver did not terminate");
+    }
+    int64_t iters_total = 0, switches = 0;
+    for (int64_t j = 0; j < K; ++j) {
+        iters_total += hs[j].iter;
+        switches += hs[j].switches;
+    }
+
+    // outputs
+    if (need_full && rq.Xout && !x_is_out) {
+        if (o.precision == 1) HIPCHK(launch_store_solution(s, rq.Xout, st));
+        else HIPCHK(hipMemcpyAsync(rq.Xout, s.X, KM * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    }
+    if (rq.keepX) {
+        HIPCHK(rq.keepX->alloc(KM * n * sizeof(double2)) == hipSuccess ? hipSuccess : hipErrorOutOfMemory);
+        if (o.precision == 1) HIPCHK(launch_store_solution(s, rq.keepX->as<double2>(), st));
+        else HIPCHK(hipMemcpyAsync(rq.keepX->ptr, s.X, KM * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    }
+    if (rq.Gout) {
+        // gather from full FP64 storage (or the projection)
+        SolveDev g = s;
+        if (need_full) {
+            if (o.precision == 0) g.X = s.X;
+            else if (rq.keepX) g.X = rq.keepX->ptr;
+            else return fail(SCOCG_EINVAL, "FP32 greens_diag needs projection mode");
+        }
+        HIPCHK(launch_gather_diag(g, bidx.as<int64_t>(), rq.Gout, st));
+    }
+    HIPCHK(hipEventRecord(ev_t1, st));
+
+    // report
+    std::vector<int32_t> h_it(KM), h_st(KM);
+    std::vector<double> h_res(KM), h_true(KM, -1.0);
+    HIPCHK(hipMemcpyAsync(h_it.data(), s.iters, KM * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_st.data(), s.pstatus, KM * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_res.data(), s.res, KM * sizeof(double), hipMemcpyDeviceToHost, st));
+    unsigned long long h_stats[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(h_stats, s.stats, sizeof(h_stats), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    g_timing.update_bytes = (double)h_stats[0];
+    float tot_ms = 0;
+    HIPCHK(hipEventElapsedTime(&tot_ms, ev_t0, ev_t1));
+    g_timing.total_ms = tot_ms;
+    g_timing.iterations = iters_total;
+    g_timing.blocks = blocks;
+    g_timing.switches = switches;
+
+    if (o.check_true && need_full) {
+        const double2 *X64 = nullptr;
+        DevBuf tmp;
+        if (o.precision == 0) X64 = (const double2 *)s.X;
+        else if (rq.Xout) X64 = rq.Xout;
+        else if (rq.keepX) X64 = rq.keepX->as<double2>();
+        if (X64) {
+            DevBuf part, outr;
+            const int64_t gx = (H.nslices + 3) / 4;
+            ALLOC(part, KM * gx * sizeof(double));
+            ALLOC(outr, KM * sizeof(double));
+            HIPCHK(launch_true_residual(s, H, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, X64,
+                                        part.as<double>(), outr.as<double>(), st));
+            HIPCHK(hipMemcpyAsync(h_true.data(), outr.ptr, KM * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    }
+    int rc = SCOCG_OK;
+    for (size_t p = 0; p < KM; ++p) {
+        if (h_st[p] == PAIR_BREAKDOWN) rc = SCOCG_EBREAKDOWN;
+        else if (h_st[p] == PAIR_NOCONV && !fixed && rc == SCOCG_OK) rc = SCOCG_ENOCONV;
+    }
+    if (rq.rep) {
+        for (size_t p = 0; p < KM; ++p) {
+            rq.rep[p].iters = h_it[p];
+            rq.rep[p].status = (fixed && h_st[p] == PAIR_NOCONV) ? SCOCG_OK : h_st[p];
+            rq.rep[p].rel_res_recursive = h_res[p];
+            rq.rep[p].rel_res_true = h_true[p];
+        }
+    }
+    if (rc == SCOCG_EBREAKDOWN) g_err = "COCG breakdown on at least one pair";
+    else if (rc == SCOCG_ENOCONV) g_err = "at least one pair did not converge";
+    return rc;
+#undef ALLOC
+}
+
+}  // namespace
+
+extern "C" int shifted_cocg_solve(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const double *B,
+                                  const scocg_opts *o, double *X, scocg_pair_report *rep, scocg_tape_t *tape,
+                                  void *stream)
+{
+    g_err.clear();
+    if (!H || !z || !B || !o) return fail(SCOCG_EINVAL, "null argument");
+    const bool want_tape = tape && o->keep_tape;
+    if (!X && !want_tape) return fail(SCOCG_EINVAL, "X is null and no tape was requested");
+    SolveRequest rq{};
+    rq.H = H;
+    rq.M = n_shift;
+    rq.K = n_rhs;
+    rq.z = z;
+    rq.B = (const double2 *)B;
+    rq.o = *o;
+    rq.Xout = (double2 *)X;
+    rq.projection = false;
+    rq.rep = rep;
+    scocg_tape *tp = nullptr;
+    if (want_tape) {
+        tp = new scocg_tape();
+        rq.keepX = &tp->X;
+    }
+    int rc = solve(rq, (hipStream_t)stream);
+    if (tp) {
+        if (rc == SCOCG_OK || rc == SCOCG_ENOCONV) {
+            tp->H = H;
+            tp->K = n_rhs;
+            tp->M = n_shift;
+            tp->n = H->d.n;
+            *tape = tp;
+        } else {
+            delete tp;
+        }
+    }
+    return rc;
+}
+
+extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,
+                           const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream)
+{
+    g_err.clear();
+    if (!H || !z || !rhs_idx || !o || !G) return fail(SCOCG_EINVAL, "null argument");
+    for (int64_t j = 0; j < n_rhs; ++j)
+        if (rhs_idx[j] < 0 || rhs_idx[j] >= H->d.n) return fail(SCOCG_EINVAL, "rhs_idx out of range");
+    const bool want_tape = tape && o->keep_tape;
+    SolveRequest rq{};
+    rq.H = H;
+    rq.M = n_shift;
+    rq.K = n_rhs;
+    rq.z = z;
+    rq.B = nullptr;
+    rq.unit_idx = rhs_idx;
+    rq.o = *o;
+    rq.Xout = nullptr;
+    rq.projection = !want_tape;
+    rq.Gout = (double2 *)G;
+    rq.rep = rep;
+    scocg_tape *tp = nullptr;
+    if (want_tape) {
+        tp = new scocg_tape();
+        rq.keepX = &tp->X;
+    }
+    int rc = solve(rq, (hipStream_t)stream);
+    if (tp) {
+        if (rc == SCOCG_OK || rc == SCOCG_ENOCONV) {
+            tp->H = H;
+            tp->K = n_rhs;
+            tp->M = n_shift;
+            tp->n = H->d.n;
+            *tape = tp;
+        } else {
+            delete tp;
+        }
+    }
+    return rc;
+}
+
+extern "C" int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double *z, const double *w, int64_t n_rhs,
+                                     const int64_t *rhs_idx, const scocg_opts *o, int64_t rhs_batch, double *rho_nnz,
+                                     double *E_band, double *dE_dval, void *stream)
+{
+    g_err.clear();
+    if (!H || !z || !w || !rhs_idx || !o || !E_band) return fail(SCOCG_EINVAL, "null argument");
+    if (n_quad <= 0 || n_rhs <= 0) return fail(SCOCG_EINVAL, "n_quad and n_rhs must be positive");
+    const DevCSR &d = H->d;
+    for (int64_t j = 0; j < n_rhs; ++j)
+        if (rhs_idx[j] < 0 || rhs_idx[j] >= d.n) return fail(SCOCG_EINVAL, "rhs_idx out of range");
+    int64_t maxrow = 0;
+    for (int64_t i = 0; i < d.n; ++i) maxrow = std::max<int64_t>(maxrow, H->h_row_ptr[i + 1] - H->h_row_ptr[i]);
+    if (dE_dval && maxrow > 32) return fail(SCOCG_EINVAL, "dE_dval supports rows of at most 32 entries");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t batch = rhs_batch > 0 ? rhs_batch : std::min<int64_t>(n_rhs, 256);
+    batch = std::min(batch, n_rhs);
+    DevBuf bw, bz, bidx, bX, bEp, bc;
+    if (bw.alloc(n_quad * sizeof(double2)) || bz.alloc(n_quad * sizeof(double2)) ||
+        bidx.alloc(batch * sizeof(int64_t)) || bX.alloc((size_t)batch * n_quad * d.n * sizeof(double2)) ||
+        bEp.alloc(batch * sizeof(double)) || bc.alloc((size_t)batch * n_quad * sizeof(double2)))
+        return fail(SCOCG_ENOMEM, "density_matrix_energy: device allocation failed");
+    HIPCHK(hipMemcpyAsync(bw.ptr, w, n_quad * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bz.ptr, z, n_quad * sizeof(double2), hipMemcpyHostToDevice, st));
+    int rc_all = SCOCG_OK;
+    for (int64_t j0 = 0; j0 < n_rhs; j0 += batch) {
+        const int64_t kb = std::min(batch, n_rhs - j0);
+        SolveRequest rq{};
+        rq.H = H;
+        rq.M = n_quad;
+        rq.K = kb;
+        rq.z = z;
+        rq.B = nullptr;
+        rq.unit_idx = rhs_idx + j0;
+        rq.o = *o;
+        rq.o.check_true = 0;
+        rq.Xout = bX.as<double2>();
+        rq.projection = false;
+        int rc = solve(rq, st);
+        if (rc != SCOCG_OK && rc != SCOCG_ENOCONV) return rc;
+        if (rc == SCOCG_ENOCONV) rc_all = SCOCG_ENOCONV;
+        HIPCHK(hipMemcpyAsync(bidx.ptr, rhs_idx + j0, kb * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_density_rho(d.n, kb, n_quad, bX.as<double2>(), bidx.as<int64_t>(), d.d_row_ptr, d.d_col,
+                                  bw.as<double2>(), bz.as<double2>(), rho_nnz, bEp.as<double>(), E_band, st));
+        if (dE_dval) {
+            HIPCHK(launch_pair_weights(0, kb, n_quad, bw.as<double2>(), bz.as<double2>(), nullptr, bc.as<double2>(), st));
+            HIPCHK(launch_pair_outer(d.n, kb * n_quad, bX.as<double2>(), bc.as<double2>(), d.d_row_ptr, d.d_col,
+                                     (int)maxrow, dE_dval, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (rc_all == SCOCG_ENOCONV) g_err = "at least one pair did not converge";
+    return rc_all;
+}
+
+extern "C" int backward(scocg_tape_t tape, const double *grad_G, double *grad_val, void *stream)
+{
+    g_err.clear();
+    if (!tape || !grad_G || !grad_val) return fail(SCOCG_EINVAL, "null argument");
+    const DevCSR &d = tape->H->d;
+    int64_t maxrow = 0;
+    for (int64_t i = 0; i < d.n; ++i)
+        maxrow = std::max<int64_t>(maxrow, tape->H->h_row_ptr[i + 1] - tape->H->h_row_ptr[i]);
+    if (maxrow > 32) return fail(SCOCG_EINVAL, "backward supports rows of at most 32 entries");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf bc;
+    if (bc.alloc((size_t)tape->K * tape->M * sizeof(double2))) return fail(SCOCG_ENOMEM, "backward: allocation failed");
+    HIPCHK(launch_pair_weights(1, tape->K, tape->M, nullptr, nullptr, (const double2 *)grad_G, bc.as<double2>(), st));
+    HIPCHK(launch_pair_outer(d.n, tape->K * tape->M, tape->X.as<double2>(), bc.as<double2>(), d.d_row_ptr, d.d_col,
+                             (int)maxrow, grad_val, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SCOCG_OK;
+}
+
+extern "C" void tape_free(scocg_tape_t t) { delete t; }
+
+// Gauss-Legendre nodes on [-1, 1] by Newton's method on the Legendre recurrence.
+extern "C" int scocg_contour(double e_lo, double mu, int64_t n_quad, double *z, double *w)
+{
+    g_err.clear();
+    if (!z || !w || n_quad <= 0 || !(mu > e_lo)) return fail(SCOCG_EINVAL, "invalid contour arguments");
+    const double c = 0.5 * (e_lo + mu), R = 0.5 * (mu - e_lo);
+    const int64_t n = n_quad;
+    for (int64_t i = 0; i < n; ++i) {
+        double x = -std::cos(M_PI * (i + 0.75) / (n + 0.5));  // ascending nodes
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int64_t k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / (double)k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double pn = n == 1 ? x : p1, pm = n == 1 ? 1.0 : p0;
+            dp = n * (x * pn - pm) / (x * x - 1.0);
+            const double dx = pn / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        // recompute the derivative at the converged node
+        double p0 = 1.0, p1 = x;
+        for (int64_t k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / (double)k;
+            p0 = p1;
+            p1 = p2;
+        }
+        double pn = n == 1 ? x : p1, pm = n == 1 ? 1.0 : p0;
+        dp = n * (x * pn - pm) / (x * x - 1.0);
+        const double wi = 2.0 / ((1.0 - x * x) * dp * dp);
+        const double theta = 0.5 * M_PI * (x + 1.0);
+        const double wt = 0.5 * M_PI * wi;
+        const double er = std::cos(theta), ei = std::sin(theta);
+        z[2 * i] = c + R * er;
+        z[2 * i + 1] = R * ei;
+        w[2 * i] = wt * R * er / M_PI;
+        w[2 * i + 1] = wt * R * ei / M_PI;
+    }
+    return SCOCG_OK;
+}

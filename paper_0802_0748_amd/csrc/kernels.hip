@@ -1,0 +1,946 @@
+// HIP kernels of the shifted-COCG solver (gfx950, wave64).
+//
+// Data layout in HBM (n rows, K right-hand sides, M shifts):
+//   seed vectors r (ring of TB+1 slots), p, q : [K][n] complex FP64, one contiguous vector per rhs
+//   per-shift vectors x_k, p_k               : [K][M][n] (pair-major), FP64 or FP32 complex
+//   H                                        : 64-row slices, each slice stored column-slot-major
+//                                              (slot k of the 64 rows is contiguous), FP64 values
+// All reductions are fixed-order: every workgroup writes a partial, the last workgroup to
+// arrive (counter per rhs) sums the partials in index order, so results do not depend on
+// scheduling and a rhs gives the same bits whether it is solved alone or in a batch.
+#include "scocg_internal.h"
+
+// No implicit contraction: every fused multiply-add below is written out, so the
+// arithmetic (and its rounding) is the same in every template instance.
+#pragma clang fp contract(off)
+
+namespace scocg {
+
+static constexpr int WG = 256;
+
+// a * b + c with explicit fused multiply-adds
+__device__ inline double2 cfma(double2 a, double2 b, double2 c)
+{
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ inline float2 cfma(float2 a, float2 b, float2 c)
+{
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+__device__ inline double rfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float rfma(float a, float b, float c) { return fmaf(a, b, c); }
+
+// ---------------------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------------------
+__device__ inline double2 block_sum2(double2 v, double2 *sh)
+{
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = cadd(sh[t], sh[t + s]);
+        __syncthreads();
+    }
+    double2 r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double block_sum1(double v, double *sh)
+{
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double load_coherent(const double *p)
+{
+    unsigned long long v = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)v);
+}
+
+// Thread 0 has written this block's partials.  Returns true (in every thread) in the block
+// that arrives last for counter slot j; that block then sees every partial.
+__device__ inline bool arrive_last(uint32_t *cnt, int64_t j, uint32_t nblk)
+{
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        uint32_t prev = atomicAdd(&cnt[j], 1u);
+        is_last = (prev == nblk - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    bool last = is_last != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Fixed-order sum of nblk complex partials (every thread participates, result in all threads).
+__device__ inline double2 sum_partials2(const double2 *part, int64_t nblk, double2 *sh)
+{
+    double2 acc = cmk(0, 0);
+    for (int64_t b = threadIdx.x; b < nblk; b += WG) {
+        const double *pp = (const double *)(part + b);
+        acc = cadd(acc, cmk(load_coherent(pp), load_coherent(pp + 1)));
+    }
+    return block_sum2(acc, sh);
+}
+
+__device__ inline double sum_partials1(const double *part, int64_t nblk, double *sh)
+{
+    double acc = 0;
+    for (int64_t b = threadIdx.x; b < nblk; b += WG) acc += load_coherent(part + b);
+    return block_sum1(acc, sh);
+}
+
+__device__ inline void reset_counter(uint32_t *cnt, int64_t j)
+{
+    if (threadIdx.x == 0) __hip_atomic_store(&cnt[j], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline bool seed_running(const SeedState &st, int TB)
+{
+    return st.status == SEED_RUNNING && st.step < TB;
+}
+
+__device__ inline double2 *ring_slot(const SolveDev &s, int slot, int64_t j)
+{
+    return s.ring + ((int64_t)slot * s.K + j) * s.n;
+}
+
+// ---------------------------------------------------------------------------------------
+// initialisation: r_0 = b, p = 0, rho = b.b, ||b||, seed state
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restrict__ B,
+                                             const int64_t *__restrict__ unit_idx,
+                                             const int32_t *__restrict__ seed_idx, int32_t limit)
+{
+    __shared__ double2 sh2[WG];
+    __shared__ double sh1[WG];
+    const int64_t j = blockIdx.y;
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double2 b = cmk(0, 0);
+    if (row < s.n) {
+        if (B) b = B[j * s.n + row];
+        else b = cmk(row == unit_idx[j] ? 1.0 : 0.0, 0.0);
+        ring_slot(s, 0, j)[row] = b;
+        s.p[j * s.n + row] = cmk(0, 0);
+    }
+    double2 bb = block_sum2(cmul(b, b), sh2);
+    double nn = block_sum1(cabs2(b), sh1);
+    if (threadIdx.x == 0) {
+        s.part2[j * s.nblk + blockIdx.x] = bb;
+        s.part1[j * s.nblk + blockIdx.x] = nn;
+    }
+    if (!arrive_last(s.cnt, j, (uint32_t)s.nblk)) return;
+    double2 rho = sum_partials2(s.part2 + j * s.nblk, s.nblk, sh2);
+    double nb = sqrt(sum_partials1(s.part1 + j * s.nblk, s.nblk, sh1));
+    if (threadIdx.x == 0) {
+        SeedState st;
+        int sd = seed_idx[j];
+        st.zs = s.z[sd];
+        st.alpha_prev = cmk(1, 0);
+        st.beta_prev = cmk(0, 0);
+        st.rho = rho;
+        st.a0 = cmk(1, 0);
+        st.b0 = cmk(0, 0);
+        st.inv_pt = cmk(1, 0);
+        st.nb = nb;
+        st.rnorm = nb;
+        st.seed = sd;
+        st.iter = 0;
+        st.step = 0;
+        st.base = 0;
+        st.status = nb > 0 ? SEED_RUNNING : SEED_STOPPED;
+        st.sw_target = -1;
+        st.n_active = nb > 0 ? (int32_t)s.M : 0;
+        st.switches = 0;
+        st.limit = limit;
+        st.pad = 0;
+        s.seed[j] = st;
+    }
+    reset_counter(s.cnt, j);
+}
+
+__global__ void __launch_bounds__(WG) k_init_pairs(SolveDev s)
+{
+    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (pair >= s.K * s.M) return;
+    const int64_t j = pair / s.M;
+    const bool live = s.seed[j].nb > 0;
+    s.pi[pair] = cmk(1, 0);
+    s.pi_prev[pair] = cmk(1, 0);
+    s.beta_k[pair] = cmk(0, 0);
+    s.res[pair] = live ? 1.0 : 0.0;
+    s.iters[pair] = 0;
+    s.pstatus[pair] = live ? PAIR_NOCONV : PAIR_OK;
+    s.active[pair] = live ? 1 : 0;
+    s.nact[pair] = 0;
+    if (s.Xproj) s.Xproj[pair] = cmk(0, 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// seed iteration, step 1: p_n = r_n + beta_{n-1} p_{n-1}
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_p_update(SolveDev s)
+{
+    const int64_t j = blockIdx.y;
+    const SeedState st = s.seed[j];
+    if (!seed_running(st, s.TB)) return;
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (row >= s.n) return;
+    const int slot = (st.base + st.step) % (s.TB + 1);
+    const double2 r = ring_slot(s, slot, j)[row];
+    double2 *pp = s.p + j * s.n + row;
+    const double2 p = *pp;
+    const double2 b = st.beta_prev;
+    *pp = cfma(b, p, r);
+}
+
+// ---------------------------------------------------------------------------------------
+// seed iteration, step 2: q = (z_s 1 - H) p, p.q, alpha_n = rho_n / (p.q)
+// One wave per 64-row slice, four slices per workgroup.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_spmv(SolveDev s, const int64_t *__restrict__ slice_ptr,
+                                             const int32_t *__restrict__ slice_w,
+                                             const int32_t *__restrict__ ell_col,
+                                             const double *__restrict__ ell_val, int64_t nslices)
+{
+    __shared__ double2 sh2[WG];
+    const int64_t j = blockIdx.y;
+    const SeedState st = s.seed[j];
+    if (!seed_running(st, s.TB)) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t row = slice * 64 + lane;
+    const double2 *pj = s.p + j * s.n;
+    double2 pq = cmk(0, 0);
+    if (slice < nslices) {
+        const int64_t off = slice_ptr[slice];
+        const int w = slice_w[slice];
+        double ax = 0, ay = 0;
+        for (int k = 0; k < w; ++k) {
+            const int c = ell_col[off + (int64_t)k * 64 + lane];
+            const double v = ell_val[off + (int64_t)k * 64 + lane];
+            const double2 pc = pj[c];
+            ax = fma(v, pc.x, ax);
+            ay = fma(v, pc.y, ay);
+        }
+        if (row < s.n) {
+            const double2 pr = pj[row];
+            const double2 qv = cfma(st.zs, pr, make_double2(-ax, -ay));
+            s.q[j * s.n + row] = qv;
+            pq = cmul(pr, qv);
+        }
+    }
+    pq = block_sum2(pq, sh2);
+    if (threadIdx.x == 0) s.part2[j * s.nblk + blockIdx.x] = pq;
+    if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
+    const double2 tot = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
+    if (threadIdx.x == 0) {
+        if (cis0(tot) || cis0(st.rho)) {
+            s.seed[j].status = SEED_BREAKDOWN;
+        } else {
+            s.ahist[j * s.TB + st.step] = cdiv(st.rho, tot);
+        }
+    }
+    reset_counter(s.cnt, j);
+}
+
+// ---------------------------------------------------------------------------------------
+// seed iteration, step 3: r_{n+1} = r_n - alpha_n q, rho_{n+1}, ||r_{n+1}||, beta_n
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_r_update(SolveDev s)
+{
+    __shared__ double2 sh2[WG];
+    __shared__ double sh1[WG];
+    const int64_t j = blockIdx.y;
+    const SeedState st = s.seed[j];
+    if (!seed_running(st, s.TB)) return;
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int slot = (st.base + st.step) % (s.TB + 1);
+    const int nslot = (slot + 1) % (s.TB + 1);
+    const double2 a = s.ahist[j * s.TB + st.step];
+    double2 rr = cmk(0, 0);
+    double nn = 0;
+    if (row < s.n) {
+        const double2 r = ring_slot(s, slot, j)[row];
+        const double2 q = s.q[j * s.n + row];
+        const double2 rn = cfma(make_double2(-a.x, -a.y), q, r);
+        ring_slot(s, nslot, j)[row] = rn;
+        rr = cmul(rn, rn);
+        nn = cabs2(rn);
+    }
+    rr = block_sum2(rr, sh2);
+    nn = block_sum1(nn, sh1);
+    if (threadIdx.x == 0) {
+        s.part2[j * s.nblk + blockIdx.x] = rr;
+        s.part1[j * s.nblk + blockIdx.x] = nn;
+    }
+    if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
+    const double2 rho_new = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
+    const double rnorm = sqrt(sum_partials1(s.part1 + j * s.nblk, gridDim.x, sh1));
+    if (threadIdx.x == 0) {
+        const double2 beta = cdiv(rho_new, st.rho);
+        s.bhist[j * s.TB + st.step] = beta;
+        s.rnhist[j * s.TB + st.step] = rnorm;
+        SeedState *w = s.seed + j;
+        w->alpha_prev = a;
+        w->beta_prev = beta;
+        w->rho = rho_new;
+        w->rnorm = rnorm;
+        const int32_t it = st.iter + 1;
+        w->iter = it;
+        w->step = st.step + 1;
+        if (it >= st.limit) w->status = SEED_LIMIT;
+        else if (!s.fixed && s.switching && rnorm / st.nb < s.tol) w->status = SEED_PAUSED;
+    }
+    reset_counter(s.cnt, j);
+}
+
+// ---------------------------------------------------------------------------------------
+// shift scalars for the steps of the finished block (one thread per (rhs, shift) pair):
+//   pi_{n+1} = (1 + alpha_n sigma) pi_n + (alpha_n beta_{n-1} / alpha_{n-1}) (pi_n - pi_{n-1})
+//   alpha^k_n = (pi_n / pi_{n+1}) alpha_n,  beta^k_n = (pi_n / pi_{n+1})^2 beta_n
+// and the coefficients of the deferred vector update of step n:
+//   (alpha^k_n, beta^k_{n-1}, 1 / pi_n).  Convergence: ||r_{n+1}|| / (|pi_{n+1}| ||b||) < tol.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
+{
+    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (pair >= s.K * s.M) return;
+    const int64_t j = pair / s.M, k = pair % s.M;
+    const SeedState st = s.seed[j];
+    const int ns = st.step;
+    if (!s.active[pair] || ns == 0) {
+        s.nact[pair] = 0;
+        return;
+    }
+    const double2 sig = csub(s.z[k], st.zs);
+    double2 ap = st.a0, bp = st.b0;
+    double2 pi = s.pi[pair], pip = s.pi_prev[pair], bk = s.beta_k[pair];
+    double res = s.res[pair];
+    int act = 1, status = s.pstatus[pair], na = 0, iters = s.iters[pair];
+    double2 *cf = s.coef + pair * (int64_t)s.TB * 3;
+    for (int t = 0; t < ns; ++t) {
+        const double2 a = s.ahist[j * s.TB + t];
+        const double2 b = s.bhist[j * s.TB + t];
+        const double2 c1 = cmul(cadd(cmk(1, 0), cmul(a, sig)), pi);
+        const double2 c2 = cmul(cdiv(cmul(a, bp), ap), csub(pi, pip));
+        const double2 pin = cadd(c1, c2);
+        if (cis0(pin)) {
+            status = PAIR_BREAKDOWN;
+            act = 0;
+            break;
+        }
+        const double2 ratio = cdiv(pi, pin);
+        cf[3 * t + 0] = cmul(ratio, a);
+        cf[3 * t + 1] = bk;
+        cf[3 * t + 2] = cdiv(cmk(1, 0), pi);
+        bk = cmul(cmul(ratio, ratio), b);
+        pip = pi;
+        pi = pin;
+        na = t + 1;
+        iters = st.iter - ns + t + 1;
+        res = s.rnhist[j * s.TB + t] / (sqrt(cabs2(pi)) * st.nb);
+        ap = a;
+        bp = b;
+        if (!s.fixed && res < s.tol) {
+            act = 0;
+            status = PAIR_OK;
+            break;
+        }
+    }
+    s.pi[pair] = pi;
+    s.pi_prev[pair] = pip;
+    s.beta_k[pair] = bk;
+    s.res[pair] = res;
+    s.iters[pair] = iters;
+    s.pstatus[pair] = status;
+    s.active[pair] = act;
+    s.nact[pair] = na;
+    if (na > 0) {
+        // algorithmic bytes of this pair's deferred update: p_k (and x_k unless projected)
+        // written once, and read once unless this is the first block
+        const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;
+        const unsigned long long nv = s.X ? 2ull : 1ull;
+        const unsigned long long rw = (st.iter - ns == 0) ? 1ull : 2ull;
+        atomicAdd(&s.stats[0], nv * rw * esz * (unsigned long long)s.n);
+        atomicAdd(&s.stats[1], 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Deferred per-shift update: for each active pair and each step t < nact of the block
+//   p_k <- r_t / pi + beta^k p_k ;  x_k <- x_k + alpha^k p_k
+// x_k and p_k stay in registers across the block, so they are read and written once per
+// block instead of once per iteration.  One thread per row; a workgroup covers 256 rows of
+// one rhs and `shifts_per_wg` shifts; coefficients are uniform across the workgroup.
+// ---------------------------------------------------------------------------------------
+template <int TB, typename S>
+struct StoreT;
+template <int TB>
+struct StoreT<TB, double2> {
+    typedef double2 V;
+    typedef double R;
+};
+template <int TB>
+struct StoreT<TB, float2> {
+    typedef float2 V;
+    typedef float R;
+};
+
+template <typename V>
+__device__ inline V to_v(double2 a);
+template <>
+__device__ inline double2 to_v<double2>(double2 a) { return a; }
+template <>
+__device__ inline float2 to_v<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+
+template <int TB, typename V>
+__global__ void __launch_bounds__(WG) k_flush(SolveDev s, int ngroups)
+{
+    const int64_t j = blockIdx.y / ngroups;
+    const int g = blockIdx.y % ngroups;
+    const SeedState st = s.seed[j];
+    const int ns = st.step;
+    if (ns == 0) return;
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (row >= s.n) return;
+    const bool fresh = (st.iter - ns) == 0;
+    V r[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        if (t < ns) r[t] = to_v<V>(ring_slot(s, (st.base + t) % (TB + 1), j)[row]);
+        else r[t] = to_v<V>(cmk(0, 0));
+    }
+    const int G = s.shifts_per_wg;
+    const int64_t k0 = (int64_t)g * G;
+    const int64_t k1 = min(k0 + G, s.M);
+    V *X = (V *)s.X;
+    V *P = (V *)s.P;
+    const int64_t prow = s.Xproj ? s.proj_row[j] : -1;
+    for (int64_t k = k0; k < k1; ++k) {
+        const int64_t pair = j * s.M + k;
+        const int na = s.nact[pair];
+        if (na == 0) continue;
+        const int64_t idx = pair * s.n + row;
+        V x, p;
+        if (fresh) {
+            x = to_v<V>(cmk(0, 0));
+            p = x;
+        } else {
+            p = P[idx];
+            if (X) x = X[idx];
+            else x = (row == prow) ? to_v<V>(s.Xproj[pair]) : to_v<V>(cmk(0, 0));
+        }
+        const double2 *cf = s.coef + pair * (int64_t)TB * 3;
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            if (t < na) {
+                const V a = to_v<V>(cf[3 * t + 0]);
+                const V b = to_v<V>(cf[3 * t + 1]);
+                const V c = to_v<V>(cf[3 * t + 2]);
+                // p = c r_t + b p ;  x = x + a p
+                V bp;
+                bp.x = b.x * p.x;
+                bp.y = b.x * p.y;
+                bp.x = rfma(-b.y, p.y, bp.x);
+                bp.y = rfma(b.y, p.x, bp.y);
+                p = cfma(c, r[t], bp);
+                x = cfma(a, p, x);
+            }
+        }
+        P[idx] = p;
+        if (X) X[idx] = x;
+        else if (row == prow) s.Xproj[pair] = make_double2((double)x.x, (double)x.y);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// End of block, one workgroup per rhs: stop / switch decisions (Sec. 3.3 seed switching).
+// The new seed t is the active shift with the largest residual (lowest index on ties);
+// pi_k <- pi_k / pi_t, pi_{k,prev} <- pi_{k,prev} / pi_{t,prev}, alpha_prev <- alpha^t_n,
+// beta_prev <- beta^t_n, z_s <- z_t.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
+{
+    __shared__ int sh_cnt[WG];
+    __shared__ int sh_brk[WG];
+    __shared__ double sh_res[WG];
+    __shared__ int sh_idx[WG];
+    __shared__ int dec_switch, dec_brk;
+    const int64_t j = blockIdx.x;
+    const SeedState st = s.seed[j];
+    const int tid = threadIdx.x;
+    int cnt = 0, brk = 0, bi = -1;
+    double br = -1;
+    for (int64_t k = tid; k < s.M; k += WG) {
+        const int64_t pair = j * s.M + k;
+        if (s.active[pair]) {
+            cnt++;
+            const double r = s.res[pair];
+            if (r > br) {
+                br = r;
+                bi = (int)k;
+            }
+        }
+        if (s.pstatus[pair] == PAIR_BREAKDOWN) brk = 1;
+    }
+    sh_cnt[tid] = cnt;
+    sh_brk[tid] = brk;
+    sh_res[tid] = br;
+    sh_idx[tid] = bi;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+            sh_cnt[tid] += sh_cnt[tid + h];
+            sh_brk[tid] |= sh_brk[tid + h];
+            const double r2 = sh_res[tid + h];
+            const int i2 = sh_idx[tid + h];
+            if (i2 >= 0 && (r2 > sh_res[tid] || (r2 == sh_res[tid] && (sh_idx[tid] < 0 || i2 < sh_idx[tid])))) {
+                sh_res[tid] = r2;
+                sh_idx[tid] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int n_active = sh_cnt[0];
+        SeedState w = st;
+        int sw = -1, mb = 0;
+        if (st.status == SEED_STOPPED) {
+            // finished earlier
+        } else if (n_active == 0) {
+            w.status = SEED_STOPPED;  // every pair has its own final status
+        } else if (st.status == SEED_BREAKDOWN || sh_brk[0]) {
+            w.status = SEED_STOPPED;  // breakdown ends every pair still active
+            mb = 1;
+        } else if (st.status == SEED_PAUSED) {
+            sw = sh_idx[0];
+            w.status = SEED_RUNNING;
+        } else if (st.status == SEED_LIMIT) {
+            w.status = SEED_STOPPED;
+        }
+        // the deferred update read the block's residual history once per row
+        if (st.step > 0) atomicAdd(&s.stats[0], (unsigned long long)st.step * 16ull * (unsigned long long)s.n);
+        w.base = (st.base + st.step) % (s.TB + 1);
+        w.step = 0;
+        w.n_active = n_active;
+        w.a0 = st.alpha_prev;
+        w.b0 = st.beta_prev;
+        w.sw_target = -1;
+        s.seed[j] = w;
+        dec_switch = (sw >= 0 && sw != st.seed) ? sw : -1;
+        dec_brk = mb;
+    }
+    __syncthreads();
+    if (dec_brk) {
+        for (int64_t k = tid; k < s.M; k += WG) {
+            const int64_t pair = j * s.M + k;
+            if (s.active[pair]) {
+                s.pstatus[pair] = PAIR_BREAKDOWN;
+                s.active[pair] = 0;
+            }
+        }
+    }
+    const int t = dec_switch;
+    if (t < 0) return;
+    const double2 pt = s.pi[j * s.M + t];
+    const double2 ppt = s.pi_prev[j * s.M + t];
+    __syncthreads();
+    for (int64_t k = tid; k < s.M; k += WG) {
+        const int64_t pair = j * s.M + k;
+        s.pi[pair] = cdiv(s.pi[pair], pt);
+        s.pi_prev[pair] = cdiv(s.pi_prev[pair], ppt);
+    }
+    if (tid == 0) {
+        SeedState *w = s.seed + j;
+        const double2 ap = cdiv(cmul(st.alpha_prev, ppt), pt);
+        const double2 bp = s.beta_k[j * s.M + t];
+        w->alpha_prev = ap;
+        w->beta_prev = bp;
+        w->a0 = ap;
+        w->b0 = bp;
+        w->zs = s.z[t];
+        w->seed = t;
+        w->inv_pt = cdiv(cmk(1, 0), pt);
+        w->sw_target = t;
+        w->switches = st.switches + 1;
+    }
+}
+
+// r <- r / pi_t, p <- p_t (the new seed's direction), rho <- r.r
+template <typename V>
+__global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
+{
+    __shared__ double2 sh2[WG];
+    const int64_t j = blockIdx.y;
+    const SeedState st = s.seed[j];
+    if (st.sw_target < 0) return;
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double2 rr = cmk(0, 0);
+    if (row < s.n) {
+        double2 *rp = ring_slot(s, st.base, j) + row;
+        const double2 r = cmul(*rp, st.inv_pt);
+        *rp = r;
+        const V pt = ((const V *)s.P)[(j * s.M + st.sw_target) * s.n + row];
+        s.p[j * s.n + row] = make_double2((double)pt.x, (double)pt.y);
+        rr = cmul(r, r);
+    }
+    rr = block_sum2(rr, sh2);
+    if (threadIdx.x == 0) s.part2[j * s.nblk + blockIdx.x] = rr;
+    if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
+    const double2 rho = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
+    if (threadIdx.x == 0) {
+        s.seed[j].rho = rho;
+        s.seed[j].sw_target = -1;
+    }
+    reset_counter(s.cnt, j);
+}
+
+// ---------------------------------------------------------------------------------------
+// outputs
+// ---------------------------------------------------------------------------------------
+__global__ void k_zero(uint32_t *p, size_t nwords)
+{
+    const size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * WG;
+    for (size_t k = i; k < nwords; k += stride) p[k] = 0u;
+}
+
+__global__ void k_upcast(const float2 *__restrict__ src, double2 *__restrict__ dst, size_t count)
+{
+    const size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * WG;
+    for (size_t k = i; k < count; k += stride) dst[k] = make_double2((double)src[k].x, (double)src[k].y);
+}
+
+// ||b - (z_k - H) x_k||^2 partials: grid (row blocks, pairs)
+__global__ void __launch_bounds__(WG) k_true_res_part(int64_t n, int64_t M, const double2 *__restrict__ z,
+                                                      const int64_t *__restrict__ slice_ptr,
+                                                      const int32_t *__restrict__ slice_w,
+                                                      const int32_t *__restrict__ ell_col,
+                                                      const double *__restrict__ ell_val, int64_t nslices,
+                                                      const double2 *__restrict__ B,
+                                                      const int64_t *__restrict__ unit_idx,
+                                                      const double2 *__restrict__ X, double *__restrict__ part,
+                                                      int64_t nblk, int64_t pair0)
+{
+    __shared__ double sh1[WG];
+    const int64_t pair = pair0 + blockIdx.y;
+    const int64_t j = pair / M, k = pair % M;
+    const int lane = threadIdx.x & 63;
+    const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t row = slice * 64 + lane;
+    const double2 *x = X + pair * n;
+    double e = 0;
+    if (slice < nslices) {
+        const int64_t off = slice_ptr[slice];
+        const int w = slice_w[slice];
+        double ax = 0, ay = 0;
+        for (int c = 0; c < w; ++c) {
+            const int col = ell_col[off + (int64_t)c * 64 + lane];
+            const double v = ell_val[off + (int64_t)c * 64 + lane];
+            const double2 xc = x[col];
+            ax += v * xc.x;
+            ay += v * xc.y;
+        }
+        if (row < n) {
+            const double2 zx = cmul(z[k], x[row]);
+            double2 b;
+            if (B) b = B[j * n + row];
+            else b = cmk(row == unit_idx[j] ? 1.0 : 0.0, 0.0);
+            const double dx = b.x - (zx.x - ax), dy = b.y - (zx.y - ay);
+            e = dx * dx + dy * dy;
+        }
+    }
+    e = block_sum1(e, sh1);
+    if (threadIdx.x == 0) part[pair * nblk + blockIdx.x] = e;
+}
+
+__global__ void k_true_res_final(int64_t KM, int64_t M, const double *__restrict__ part, int64_t nblk,
+                                 const SeedState *__restrict__ seed, double *__restrict__ out)
+{
+    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (pair >= KM) return;
+    double acc = 0;
+    for (int64_t b = 0; b < nblk; ++b) acc += part[pair * nblk + b];
+    const double nb = seed[pair / M].nb;
+    out[pair] = nb > 0 ? sqrt(acc) / nb : sqrt(acc);
+}
+
+// G[k][c] = x_{c,k}[rows[c]] from full storage (X [K][M][n]) or the projected values
+__global__ void k_gather_diag(int64_t K, int64_t M, int64_t n, const double2 *__restrict__ X,
+                              const double2 *__restrict__ Xproj, const int64_t *__restrict__ rows,
+                              double2 *__restrict__ G)
+{
+    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (pair >= K * M) return;
+    const int64_t j = pair / M, k = pair % M;
+    G[k * K + j] = Xproj ? Xproj[pair] : X[pair * n + rows[j]];
+}
+
+// Density matrix, band energy and energy gradient of one batch of columns.
+//   rho[e] += Re sum_k w_k x_{j,k}[col(e)]     for stored entries e of row cols_of_rhs[j]
+//   Epart[j] = Re sum_k w_k z_k x_{j,k}[cols_of_rhs[j]]
+__global__ void k_density_rho(int64_t n, int64_t K, int64_t M, const double2 *__restrict__ X,
+                              const int64_t *__restrict__ cols_of_rhs, const int64_t *__restrict__ row_ptr,
+                              const int32_t *__restrict__ col, const double2 *__restrict__ w,
+                              const double2 *__restrict__ z, double *__restrict__ rho, double *__restrict__ Epart)
+{
+    const int64_t j = blockIdx.x;
+    const int64_t b = cols_of_rhs[j];
+    const int64_t e0 = row_ptr[b], e1 = row_ptr[b + 1];
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int64_t a = col[e];
+        double acc = 0;
+        for (int64_t k = 0; k < M; ++k) {
+            const double2 x = X[(j * M + k) * n + a];
+            acc += w[k].x * x.x - w[k].y * x.y;
+        }
+        if (rho) rho[e] += acc;
+    }
+    if (threadIdx.x == 0) {
+        double acc = 0;
+        for (int64_t k = 0; k < M; ++k) {
+            const double2 x = X[(j * M + k) * n + b];
+            const double2 wz = cmul(w[k], z[k]);
+            acc += wz.x * x.x - wz.y * x.y;
+        }
+        Epart[j] = acc;
+    }
+}
+
+__global__ void k_sum_into(const double *__restrict__ part, int64_t count, double *__restrict__ out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double acc = 0;
+        for (int64_t i = 0; i < count; ++i) acc += part[i];
+        out[0] += acc;
+    }
+}
+
+// grad[e] += Re sum_p c_p x_p[a] x_p[b] for every stored entry e = (a, b); one thread per row a.
+// c_p is given per (rhs, shift) pair.  MAXW bounds the row length held in registers.
+template <int MAXW>
+__global__ void __launch_bounds__(WG) k_pair_outer(int64_t n, int64_t npairs, const double2 *__restrict__ X,
+                                                   const double2 *__restrict__ c, const int64_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, double *__restrict__ grad)
+{
+    const int64_t a = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (a >= n) return;
+    const int64_t e0 = row_ptr[a];
+    const int w = (int)(row_ptr[a + 1] - e0);
+    int cols[MAXW];
+    double acc[MAXW];
+#pragma unroll
+    for (int i = 0; i < MAXW; ++i) {
+        cols[i] = (i < w) ? col[e0 + i] : 0;
+        acc[i] = 0;
+    }
+    for (int64_t p = 0; p < npairs; ++p) {
+        const double2 *x = X + p * n;
+        const double2 xa = cmul(c[p], x[a]);
+#pragma unroll
+        for (int i = 0; i < MAXW; ++i) {
+            if (i < w) {
+                const double2 xb = x[cols[i]];
+                acc[i] += xa.x * xb.x - xa.y * xb.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXW; ++i)
+        if (i < w) grad[e0 + i] += acc[i];
+}
+
+// per-pair weights for the band-energy derivative: c_p = w_k z_k for pair p = (j, k)
+__global__ void k_pair_weights_wz(int64_t K, int64_t M, const double2 *__restrict__ w, const double2 *__restrict__ z,
+                                  double2 *__restrict__ c)
+{
+    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (p >= K * M) return;
+    const int64_t k = p % M;
+    c[p] = cmul(w[k], z[k]);
+}
+
+// per-pair weights for backward through G: c_p = conj(g[k][j])
+__global__ void k_pair_weights_conj(int64_t K, int64_t M, const double2 *__restrict__ g, double2 *__restrict__ c)
+{
+    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (p >= K * M) return;
+    const int64_t j = p / M, k = p % M;
+    const double2 v = g[k * K + j];
+    c[p] = make_double2(v.x, -v.y);
+}
+
+// ---------------------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------------------
+static inline dim3 grid2(int64_t x, int64_t y) { return dim3((unsigned)x, (unsigned)y, 1); }
+
+hipError_t launch_init(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
+                       const int32_t *seed_idx, int32_t limit, hipStream_t st)
+{
+    (void)H;
+    hipLaunchKernelGGL(k_init, grid2(s.nblk, s.K), dim3(WG), 0, st, s, B, unit_idx, seed_idx, limit);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t KM = s.K * s.M;
+    hipLaunchKernelGGL(k_init_pairs, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_p_update(const SolveDev &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_p_update, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(const SolveDev &s, const DevCSR &H, hipStream_t st)
+{
+    const int64_t gx = (H.nslices + 3) / 4;
+    hipLaunchKernelGGL(k_spmv, grid2(gx, s.K), dim3(WG), 0, st, s, H.d_slice_ptr, H.d_slice_w, H.d_ell_col,
+                       H.d_ell_val, H.nslices);
+    return hipGetLastError();
+}
+
+hipError_t launch_r_update(const SolveDev &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_r_update, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_scalars(const SolveDev &s, hipStream_t st)
+{
+    const int64_t KM = s.K * s.M;
+    hipLaunchKernelGGL(k_pair_scalars, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, s);
+    return hipGetLastError();
+}
+
+template <int TB>
+static hipError_t flush_tb(const SolveDev &s, hipStream_t st)
+{
+    const int ng = (int)((s.M + s.shifts_per_wg - 1) / s.shifts_per_wg);
+    const dim3 g = grid2(s.nblk, s.K * ng);
+    if (s.precision == 0) hipLaunchKernelGGL((k_flush<TB, double2>), g, dim3(WG), 0, st, s, ng);
+    else hipLaunchKernelGGL((k_flush<TB, float2>), g, dim3(WG), 0, st, s, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_flush(const SolveDev &s, hipStream_t st)
+{
+    switch (s.TB) {
+    case 1: return flush_tb<1>(s, st);
+    case 2: return flush_tb<2>(s, st);
+    case 4: return flush_tb<4>(s, st);
+    case 8: return flush_tb<8>(s, st);
+    case 16: return flush_tb<16>(s, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_block_finalize(const SolveDev &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_block_finalize, dim3((unsigned)s.K), dim3(WG), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_switch_vectors(const SolveDev &s, hipStream_t st)
+{
+    if (s.precision == 0) hipLaunchKernelGGL(k_switch_vectors<double2>, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    else hipLaunchKernelGGL(k_switch_vectors<float2>, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    const size_t words = bytes / 4;
+    size_t blocks = (words + WG - 1) / WG;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(WG), 0, st, (uint32_t *)ptr, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_solution(const SolveDev &s, double2 *Xout, hipStream_t st)
+{
+    if (s.precision == 0) return hipSuccess;
+    const size_t count = (size_t)(s.K * s.M * s.n);
+    size_t blocks = (count + WG - 1) / WG;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_upcast, dim3((unsigned)blocks), dim3(WG), 0, st, (const float2 *)s.X, Xout, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_true_residual(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
+                                const double2 *X64, double *part, double *out_res, hipStream_t st)
+{
+    const int64_t gx = (H.nslices + 3) / 4;
+    const int64_t KM = s.K * s.M;
+    const int64_t chunk = 32768;
+    for (int64_t p0 = 0; p0 < KM; p0 += chunk) {
+        const int64_t np = (KM - p0) < chunk ? (KM - p0) : chunk;
+        hipLaunchKernelGGL(k_true_res_part, grid2(gx, np), dim3(WG), 0, st, s.n, s.M, s.z, H.d_slice_ptr,
+                           H.d_slice_w, H.d_ell_col, H.d_ell_val, H.nslices, B, unit_idx, X64, part, gx, p0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_true_res_final, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, KM, s.M, part, gx,
+                       s.seed, out_res);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_diag(const SolveDev &s, const int64_t *rows, double2 *G, hipStream_t st)
+{
+    const int64_t KM = s.K * s.M;
+    hipLaunchKernelGGL(k_gather_diag, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, s.K, s.M, s.n,
+                       (const double2 *)s.X, s.Xproj, rows, G);
+    return hipGetLastError();
+}
+
+// Observable kernels used by the host driver directly.
+hipError_t launch_density_rho(int64_t n, int64_t K, int64_t M, const double2 *X, const int64_t *cols_of_rhs,
+                              const int64_t *row_ptr, const int32_t *col, const double2 *w, const double2 *z,
+                              double *rho, double *Epart, double *Eacc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_density_rho, dim3((unsigned)K), dim3(64), 0, st, n, K, M, X, cols_of_rhs, row_ptr, col, w,
+                       z, rho, Epart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, st, Epart, K, Eacc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_weights(int mode, int64_t K, int64_t M, const double2 *w, const double2 *z,
+                               const double2 *g, double2 *c, hipStream_t st)
+{
+    const int64_t KM = K * M;
+    if (mode == 0) hipLaunchKernelGGL(k_pair_weights_wz, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, K, M, w, z, c);
+    else hipLaunchKernelGGL(k_pair_weights_conj, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, K, M, g, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_outer(int64_t n, int64_t npairs, const double2 *X, const double2 *c, const int64_t *row_ptr,
+                             const int32_t *col, int max_row, double *grad, hipStream_t st)
+{
+    const dim3 g((unsigned)((n + WG - 1) / WG));
+    if (max_row <= 8) hipLaunchKernelGGL(k_pair_outer<8>, g, dim3(WG), 0, st, n, npairs, X, c, row_ptr, col, grad);
+    else if (max_row <= 20) hipLaunchKernelGGL(k_pair_outer<20>, g, dim3(WG), 0, st, n, npairs, X, c, row_ptr, col, grad);
+    else if (max_row <= 32) hipLaunchKernelGGL(k_pair_outer<32>, g, dim3(WG), 0, st, n, npairs, X, c, row_ptr, col, grad);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace scocg

@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP kernels and the host driver of libscocg.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scocg {
+
+// ---- complex helpers (double2 / float2 as interleaved re, im) ----
+__host__ __device__ inline double2 cmk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline bool cis0(double2 a) { return a.x == 0.0 && a.y == 0.0; }
+// a / b with Smith's scaling (avoids overflow of |b|^2 for large |b|).
+__host__ __device__ inline double2 cdiv(double2 a, double2 b)
+{
+    if (fabs(b.x) >= fabs(b.y)) {
+        double r = b.y / b.x, d = b.x + b.y * r;
+        return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+    } else {
+        double r = b.x / b.y, d = b.x * r + b.y;
+        return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+    }
+}
+__host__ __device__ inline float2 cmulf(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// ---- per right-hand-side seed state ----
+enum SeedStatus : int32_t {
+    SEED_RUNNING = 0,   // iterating
+    SEED_PAUSED = 1,    // seed converged: switch at the end of this block
+    SEED_LIMIT = 2,     // iteration limit reached
+    SEED_STOPPED = 3,   // finished (all pairs frozen or limit)
+    SEED_BREAKDOWN = 4  // COCG breakdown
+};
+
+struct SeedState {
+    double2 zs;          // seed shift
+    double2 alpha_prev;  // alpha_{n-1}
+    double2 beta_prev;   // beta_{n-1}
+    double2 rho;         // r.r (unconjugated)
+    double2 a0, b0;      // alpha_{n0-1}, beta_{n0-1} at the start of the current block
+    double2 inv_pt;      // 1 / pi_t of a pending seed switch
+    double nb;           // ||b||
+    double rnorm;        // ||r||
+    int32_t seed;        // seed shift index
+    int32_t iter;        // iterations done
+    int32_t step;        // iterations done in the current block
+    int32_t base;        // ring slot of r at the start of the block
+    int32_t status;
+    int32_t sw_target;   // pending switch target or -1
+    int32_t n_active;    // pairs still active after the last block
+    int32_t switches;    // number of seed switches so far
+    int32_t limit;       // iteration limit (max_iter or fixed_iter)
+    int32_t pad;
+};
+
+enum PairStatus : int32_t { PAIR_OK = 0, PAIR_BREAKDOWN = 4, PAIR_NOCONV = 5 };
+
+// ---- device-side matrix ----
+struct DevCSR {
+    int64_t n, nnz;
+    int64_t nslices;      // 64-row slices
+    int64_t ell_nnz;      // padded entries
+    int64_t *d_slice_ptr; // [nslices+1] offsets into ell arrays
+    int32_t *d_slice_w;   // [nslices] width (max row length) of each slice
+    int32_t *d_ell_col;   // [ell_nnz] column, slice-major then lane
+    double *d_ell_val;    // [ell_nnz]
+    int32_t *d_ell_pos;   // [ell_nnz] CSR position of each slot (-1 padding)
+    int64_t *d_row_ptr;   // [n+1] CSR pattern (int64)
+    int32_t *d_col;       // [nnz]
+    double *d_val;        // [nnz] CSR values
+    double trace;         // Tr(H) (host side)
+    int64_t *h_row_ptr;   // host copies of the pattern (for value updates)
+    int64_t *h_col;
+    int64_t *h_ell_src;   // [ell_nnz] CSR position of each slot (host)
+    int max_w;            // widest slice
+};
+
+// ---- launch wrappers (kernels.hip) ----
+struct SolveDev {
+    int64_t n, K, M;
+    int TB;                    // block length (ring has TB+1 slots)
+    int precision;             // 0 FP64 storage, 1 FP32
+    int fixed;                 // fixed-iteration mode
+    int switching;
+    double tol;
+    const double2 *z;          // [M]
+    SeedState *seed;           // [K]
+    double2 *ring;             // [(TB+1)][K][n]
+    double2 *p, *q;            // [K][n]
+    void *X, *P;               // [K][M][n] (double2 or float2); X may be null in projection mode
+    double2 *Xproj;            // [K][M] projected solution (projection mode) or null
+    const int64_t *proj_row;   // [K] row kept in projection mode
+    double2 *pi, *pi_prev, *beta_k; // [K*M]
+    double *res;               // [K*M]
+    int32_t *iters, *pstatus, *active, *nact; // [K*M]
+    double2 *ahist, *bhist;    // [K][TB]
+    double *rnhist;            // [K][TB]
+    double2 *coef;             // [K*M][TB][3]
+    double2 *part2;            // [K][nblk] complex partials
+    double *part1;             // [K][nblk] real partials
+    uint32_t *cnt;             // [K] last-block counters
+    int64_t nblk;              // row blocks of 256
+    int shifts_per_wg;
+    unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
+};
+
+hipError_t launch_init(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
+                       const int32_t *seed_idx, int32_t limit, hipStream_t st);
+hipError_t launch_p_update(const SolveDev &s, hipStream_t st);
+hipError_t launch_spmv(const SolveDev &s, const DevCSR &H, hipStream_t st);
+hipError_t launch_r_update(const SolveDev &s, hipStream_t st);
+hipError_t launch_pair_scalars(const SolveDev &s, hipStream_t st);
+hipError_t launch_flush(const SolveDev &s, hipStream_t st);
+hipError_t launch_block_finalize(const SolveDev &s, hipStream_t st);
+hipError_t launch_switch_vectors(const SolveDev &s, hipStream_t st);
+hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t st);
+hipError_t launch_store_solution(const SolveDev &s, double2 *Xout, hipStream_t st);
+hipError_t launch_true_residual(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
+                                const double2 *X64, double *part, double *out_res, hipStream_t st);
+hipError_t launch_gather_diag(const SolveDev &s, const int64_t *rows, double2 *G, hipStream_t st);
+hipError_t launch_density_rho(int64_t n, int64_t K, int64_t M, const double2 *X, const int64_t *cols_of_rhs,
+                              const int64_t *row_ptr, const int32_t *col, const double2 *w, const double2 *z,
+                              double *rho, double *Epart, double *Eacc, hipStream_t st);
+hipError_t launch_pair_weights(int mode, int64_t K, int64_t M, const double2 *w, const double2 *z,
+                               const double2 *g, double2 *c, hipStream_t st);
+hipError_t launch_pair_outer(int64_t n, int64_t npairs, const double2 *X, const double2 *c, const int64_t *row_ptr,
+                             const int32_t *col, int max_row, double *grad, hipStream_t st);
+
+}  // namespace scocg

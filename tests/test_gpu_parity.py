@@ -1,0 +1,241 @@
+"""GPU (HIP library through the C ABI) against the FP64 CPU oracle."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import config1_cubic, random_sparse_symmetric, simple_cubic
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _S():
+    import paper_0802_0748_amd as S
+
+    return S
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _problem(n, seed, density=0.03):
+    rng = np.random.default_rng(seed)
+    H = random_sparse_symmetric(n, density, rng, diag_scale=2.0)
+    z = np.linspace(-2.5, 2.5, 9) + 1j * np.array([0.05, 0.3, 0.1, 0.02, 0.2, 0.5, 0.05, 0.1, 0.3])
+    B = rng.normal(size=(3, n)) + 1j * rng.normal(size=(3, n))
+    return H, z, B
+
+
+@pytest.mark.parametrize("n", [1, 37, 300, 1111])
+def test_fixed_iteration_fp64_matches_oracle(n):
+    """Fixed-iteration mode (no freezing or switching): only the summation order differs, so the
+    FP64 parity bar of 1e-10 relative applies (observed differences are around 1e-12)."""
+    S = _S()
+    Hc, z, B = _problem(n, 1)
+    H = S.Hamiltonian.from_csr(Hc)
+    iters = 1 if n == 1 else min(25, n // 3)  # stay well before convergence (rounding noise after it)
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), fixed_iter=iters, seed_index=2, block=4)
+    assert rc == 0
+    Xg = X.cpu().numpy()
+    for j in range(B.shape[0]):
+        ref = O.shifted_cocg(Hc, z, B[j], fixed_iter=iters, seed_index=2)
+        for k in range(len(z)):
+            assert _rel(Xg[j, k], ref["X"][k]) < 1e-10, (j, k)
+        assert np.all(rep["iters"][j] == iters)
+
+
+def test_block_length_does_not_change_bits():
+    """The deferred shift update applies the same operations in the same order for any block length."""
+    S = _S()
+    Hc, z, B = _problem(300, 2)
+    H = S.Hamiltonian.from_csr(Hc)
+    Bt = torch.from_numpy(B).cuda()
+    ref = None
+    for tb in (1, 2, 4, 8, 16):
+        X, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=37, seed_index=0, block=tb)
+        Xn = X.cpu().numpy()
+        if ref is None:
+            ref = Xn
+        else:
+            assert np.array_equal(Xn, ref), tb
+
+
+def test_batched_equals_single_rhs_bitwise():
+    S = _S()
+    Hc, z, B = _problem(500, 3)
+    H = S.Hamiltonian.from_csr(Hc)
+    Xb, repb, _, _ = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=1e-10, max_iter=3000)
+    Xb = Xb.cpu().numpy()
+    for j in range(B.shape[0]):
+        X1, rep1, _, _ = S.shifted_cocg_solve(H, z, torch.from_numpy(B[j:j + 1]).cuda(), tol=1e-10, max_iter=3000)
+        assert np.array_equal(X1.cpu().numpy()[0], Xb[j])
+        assert np.array_equal(rep1["iters"][0], repb["iters"][j])
+
+
+def _bound_check(H, z, b, x_gpu, res_true_gpu, x_orc):
+    """Sec. 3.4: |x - x*| <= ||b - (z - H) x|| / Im z for real-symmetric H, so two
+    converged answers differ by at most the sum of their residual bounds."""
+    nb = np.linalg.norm(b)
+    r_orc = O.true_residual(H, z, x_orc, b)
+    bound = (res_true_gpu + r_orc) * nb / abs(z.imag)
+    return np.linalg.norm(x_gpu - x_orc), bound
+
+
+def test_production_switching_short_run_matches_oracle():
+    """Tolerance-stopped solve with seed switching on a short run (< 160 iterations).
+
+    The freeze iteration of a pair is decided by comparing a residual with the tolerance;
+    the oracle itself moves it by a few iterations when only the summation order changes
+    (same matrix with rows permuted).  So: same number of seed switches, freeze iterations
+    within 3, X to 1e-10 where the freeze iteration agrees, else within the residual bound."""
+    S = _S()
+    rng = np.random.default_rng(11)
+    L = 6
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    z = np.concatenate([np.linspace(-6, 6, 13) + 0.8j, [0.3 + 3.0j, -2 + 2.5j, 1.0 + 0.7j]])
+    B = np.zeros((2, Hc.n), dtype=complex)
+    B[0, 0] = 1
+    B[1] = rng.normal(size=Hc.n) + 1j * rng.normal(size=Hc.n)
+    H = S.Hamiltonian.from_csr(Hc)
+    tol = 1e-10
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=tol, max_iter=5000, seed_index=13,
+                                         check_true=True)
+    t = S.last_timing()
+    assert rc == 0
+    Xg = X.cpu().numpy()
+    n_sw = 0
+    n_equal = 0
+    for j in range(2):
+        ref = O.shifted_cocg(Hc, z, B[j], tol=tol, max_iter=5000, seed_index=13)
+        assert ref["ret"] == 0
+        n_sw += len(ref["switches"])
+        assert np.all(np.abs(rep["iters"][j] - ref["iters"]) <= 3), (rep["iters"][j], ref["iters"])
+        for k in range(len(z)):
+            if rep["iters"][j, k] == ref["iters"][k]:
+                n_equal += 1
+                assert _rel(Xg[j, k], ref["X"][k]) < 1e-10, (j, k)
+            else:
+                d, bound = _bound_check(Hc, z[k], B[j], Xg[j, k], rep["res_true"][j, k], ref["X"][k])
+                assert d <= bound, (j, k, d, bound)
+        assert np.all(rep["res_true"][j] < 20 * tol)
+    assert n_sw >= 2 and t["switches"] == n_sw
+    assert n_equal >= len(z)
+
+
+def test_production_switching_long_run_within_residual_bound():
+    """Long tolerance-stopped runs: the freeze iteration depends on rounding (the GPU fuses
+    multiply-adds, the oracle does not), so the answers are compared through the residual
+    error bound, and both must have converged."""
+    S = _S()
+    rng = np.random.default_rng(11)
+    L = 7
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    z = np.concatenate([np.linspace(-6, 6, 13) + 0.05j, [0.3 + 1.0j, -2 + 0.5j, 1.0 + 0.02j]])
+    B = np.zeros((2, Hc.n), dtype=complex)
+    B[0, 0] = 1
+    B[1] = rng.normal(size=Hc.n) + 1j * rng.normal(size=Hc.n)
+    H = S.Hamiltonian.from_csr(Hc)
+    tol = 1e-10
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=tol, max_iter=5000, seed_index=13,
+                                         check_true=True)
+    assert rc == 0 and S.last_timing()["switches"] >= 1
+    Xg = X.cpu().numpy()
+    for j in range(2):
+        ref = O.shifted_cocg(Hc, z, B[j], tol=tol, max_iter=5000, seed_index=13)
+        assert ref["ret"] == 0
+        assert np.all(np.abs(rep["iters"][j] - ref["iters"]) <= 0.1 * ref["iters"] + 2)
+        for k in range(len(z)):
+            d, bound = _bound_check(Hc, z[k], B[j], Xg[j, k], rep["res_true"][j, k], ref["X"][k])
+            assert d <= bound, (j, k, d, bound)
+            assert rep["res_true"][j, k] < 20 * tol
+
+
+def test_greens_diag_config1_matches_oracle():
+    """The 16^3 cubic workload, G_00(z_k) for 64 shifts at tol 1e-10 with the 3000-iteration
+    cap: greens_diag equals the full solve's diagonal bit for bit, and every shift agrees with
+    the oracle within the residual bound of the two answers."""
+    S = _S()
+    p = config1_cubic()
+    H = S.Hamiltonian.from_csr(p.H)
+    G, repg, _, rc = S.greens_diag(H, p.z, p.rhs_idx, tol=p.tol, max_iter=p.max_iter)
+    B = torch.zeros((1, p.H.n), dtype=torch.complex128, device="cuda")
+    B[0, 0] = 1
+    X, rep, _, rcx = S.shifted_cocg_solve(H, p.z, B, tol=p.tol, max_iter=p.max_iter, check_true=True)
+    Gg = G.cpu().numpy()[:, 0]
+    Xg = X.cpu().numpy()[0]
+    assert np.array_equal(Gg, Xg[:, 0])
+    assert np.array_equal(repg["iters"], rep["iters"])
+    b = O.unit(p.H.n, 0)
+    ref = O.shifted_cocg(p.H, p.z, b, tol=p.tol, max_iter=p.max_iter)
+    conv_gpu = rep["status"][0] == 0
+    conv_orc = ref["status"] == 0
+    # the same shifts converge within the cap, except where the freeze iteration sits at the cap
+    assert np.sum(conv_gpu != conv_orc) <= 2
+    for k in range(len(p.z)):
+        d, bound = _bound_check(p.H, p.z[k], b, Xg[k], rep["res_true"][0, k], ref["X"][k])
+        assert d <= bound, (k, d, bound)
+        if conv_gpu[k] and conv_orc[k]:
+            assert abs(Gg[k] - ref["X"][k][0]) <= 2 * 20 * p.tol / p.z[k].imag
+
+
+def test_fp32_storage_matches_oracle_to_1e5():
+    S = _S()
+    rng = np.random.default_rng(5)
+    L = 8
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    z = np.linspace(-6, 6, 16) + 0.1j
+    B = np.zeros((1, Hc.n), dtype=complex)
+    B[0, 5] = 1
+    H = S.Hamiltonian.from_csr(Hc)
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=1e-8, max_iter=3000, precision="fp32",
+                                         check_true=True)
+    Xg = X.cpu().numpy()[0]
+    ref = O.shifted_cocg(Hc, z, B[0], tol=1e-12, max_iter=3000)
+    errs = [_rel(Xg[k], ref["X"][k]) for k in range(len(z))]
+    print("fp32 storage relative errors:", np.array(errs))
+    assert max(errs) < 1e-5
+
+
+def test_zero_rhs_and_breakdown():
+    S = _S()
+    rng = np.random.default_rng(0)
+    Hc = random_sparse_symmetric(70, 0.1, rng)
+    H = S.Hamiltonian.from_csr(Hc)
+    z = np.array([0.3 + 0.1j, 1.0 + 0.2j])
+    B = np.zeros((2, 70), dtype=complex)
+    B[1, 0] = 1
+    B[1, 1] = 1j  # b.b = 0: COCG breaks down at the first step
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=1e-10, allow_breakdown=True)
+    assert rc == 4
+    assert np.all(X.cpu().numpy()[0] == 0)
+    assert np.all(rep["status"][0] == 0) and np.all(rep["status"][1] == 4)
+
+
+def test_iteration_limit_reports_noconv():
+    S = _S()
+    Hc, z, B = _problem(200, 4)
+    H = S.Hamiltonian.from_csr(Hc)
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=1e-12, max_iter=3)
+    assert rc == 5
+    assert np.all(rep["iters"] == 3)
+    ref = O.shifted_cocg(Hc, z, B[0], tol=1e-12, max_iter=3)
+    for k in range(len(z)):
+        assert _rel(X.cpu().numpy()[0, k], ref["X"][k]) < 1e-12
+
+
+def test_invalid_arguments_raise():
+    S = _S()
+    from paper_0802_0748_amd._capi import ScocgError
+
+    Hc, z, B = _problem(50, 6)
+    v = Hc.val.copy()
+    v[0] = np.nan
+    with pytest.raises(ScocgError):
+        S.Hamiltonian(Hc.row_ptr, Hc.col, v)
+    H = S.Hamiltonian.from_csr(Hc)
+    with pytest.raises(ScocgError):
+        S.greens_diag(H, z, [50])
+    with pytest.raises(ScocgError):
+        S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), block=3)
