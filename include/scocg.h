@@ -59,7 +59,8 @@ typedef struct {
     int32_t shifts_per_wg;  /* shifts one workgroup updates in the deferred update; 0 = automatic */
     int32_t check_true;     /* 1: compute the FP64 true residual of every pair into the report */
     int32_t keep_tape;      /* 1: keep the solutions for backward() */
-    int32_t reserved[6];
+    int32_t no_graph;       /* 1: launch every kernel directly instead of replaying captured HIP graphs */
+    int32_t reserved[5];
 } scocg_opts;
 
 typedef struct {

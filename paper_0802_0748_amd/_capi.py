@@ -27,7 +27,8 @@ class Opts(ctypes.Structure):
         ("shifts_per_wg", ctypes.c_int32),
         ("check_true", ctypes.c_int32),
         ("keep_tape", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("no_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 

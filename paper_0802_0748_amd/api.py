@@ -22,7 +22,7 @@ def _require_gpu():
 
 
 def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switching=True, fixed_iter=0, block=0,
-            shifts_per_wg=0, check_true=False, keep_tape=False) -> C.Opts:
+            shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False) -> C.Opts:
     o = C.Opts()
     C.load().scocg_default_opts(ctypes.byref(o))
     o.tol = float(tol)
@@ -35,6 +35,7 @@ def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switc
     o.shifts_per_wg = int(shifts_per_wg)
     o.check_true = int(bool(check_true))
     o.keep_tape = int(bool(keep_tape))
+    o.no_graph = int(bool(no_graph))
     return o
 
 

@@ -57,6 +57,20 @@ struct DevBuf {
     T *as() const { return (T *)ptr; }
 };
 
+struct GraphPair {
+    hipStream_t cap = nullptr;
+    hipGraph_t ga = nullptr, gb = nullptr;
+    hipGraphExec_t ea = nullptr, eb = nullptr;
+    ~GraphPair()
+    {
+        if (ea) (void)hipGraphExecDestroy(ea);
+        if (eb) (void)hipGraphExecDestroy(eb);
+        if (ga) (void)hipGraphDestroy(ga);
+        if (gb) (void)hipGraphDestroy(gb);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 struct PinnedBuf {
     void *ptr = nullptr;
     ~PinnedBuf()
@@ -390,7 +404,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     ALLOC(bah, K * TB * sizeof(double2));
     ALLOC(bbh, K * TB * sizeof(double2));
     ALLOC(brn, K * TB * sizeof(double));
-    ALLOC(bcoef, KM * TB * 3 * sizeof(double2));
+    ALLOC(bcoef, KM * TB * 2 * (o.precision == 0 ? sizeof(double2) : sizeof(float2)));
     ALLOC(bp2, K * s.nblk * sizeof(double2));
     ALLOC(bp1, K * s.nblk * sizeof(double));
     ALLOC(bcnt, K * sizeof(uint32_t));
@@ -418,7 +432,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.ahist = bah.as<double2>();
     s.bhist = bbh.as<double2>();
     s.rnhist = brn.as<double>();
-    s.coef = bcoef.as<double2>();
+    s.coef = bcoef.ptr;
     s.part2 = bp2.as<double2>();
     s.part1 = bp1.as<double>();
     s.cnt = bcnt.as<uint32_t>();
@@ -448,38 +462,76 @@ int solve(SolveRequest &rq, hipStream_t st)
             for (auto e : *v) (void)hipEventDestroy(e);
         }
     } evl{&evs};
-    hipEvent_t fe0 = nullptr, fe1 = nullptr;
+    std::vector<hipEvent_t> fev;
     if (g_profiling) {
-        HIPCHK(hipEventCreate(&fe0));
-        HIPCHK(hipEventCreate(&fe1));
-        evs.push_back(fe0);
-        evs.push_back(fe1);
+        fev.resize(2 * std::max(1, 64 / TB));
+        for (auto &e : fev) {
+            HIPCHK(hipEventCreate(&e));
+            evs.push_back(e);
+        }
     }
 
+    // Each block is three launches: the captured seed iterations and shift scalars (graph A),
+    // the deferred update (timed with events when profiling), and the captured end-of-block
+    // decisions (graph B).  Graphs are captured on a private stream and replayed on `st`.
+    GraphPair gr;
+    const bool use_graph = !o.no_graph;
+    if (use_graph) {
+        HIPCHK(hipStreamCreateWithFlags(&gr.cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
+        for (int t = 0; t < TB; ++t) {
+            HIPCHK(launch_p_update(s, gr.cap));
+            HIPCHK(launch_spmv(s, H, gr.cap));
+            HIPCHK(launch_r_update(s, gr.cap));
+        }
+        HIPCHK(launch_pair_scalars(s, gr.cap));
+        HIPCHK(hipStreamEndCapture(gr.cap, &gr.ga));
+        HIPCHK(hipGraphInstantiate(&gr.ea, gr.ga, nullptr, nullptr, 0));
+        HIPCHK(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
+        HIPCHK(launch_block_finalize(s, gr.cap));
+        HIPCHK(launch_switch_vectors(s, gr.cap));
+        HIPCHK(hipStreamEndCapture(gr.cap, &gr.gb));
+        HIPCHK(hipGraphInstantiate(&gr.eb, gr.gb, nullptr, nullptr, 0));
+    }
+    // host checks the stop condition every `per_sync` blocks (about 64 iterations); blocks
+    // launched after every rhs has stopped return immediately
+    const int per_sync = std::max(1, 64 / TB);
     // worst case: every block advances one rhs by >= 1 iteration or finishes / switches one rhs
-    const int64_t max_blocks = (int64_t)K * ((int64_t)limit + 2 * M + 4) + 8;
+    const int64_t max_blocks = (int64_t)K * ((int64_t)limit + 2 * M + 4) + 8 + per_sync;
     int64_t blocks = 0;
     bool done = false;
     while (!done) {
-        for (int t = 0; t < TB; ++t) {
-            HIPCHK(launch_p_update(s, st));
-            HIPCHK(launch_spmv(s, H, st));
-            HIPCHK(launch_r_update(s, st));
+        for (int b = 0; b < per_sync; ++b) {
+            if (use_graph) {
+                HIPCHK(hipGraphLaunch(gr.ea, st));
+            } else {
+                for (int t = 0; t < TB; ++t) {
+                    HIPCHK(launch_p_update(s, st));
+                    HIPCHK(launch_spmv(s, H, st));
+                    HIPCHK(launch_r_update(s, st));
+                }
+                HIPCHK(launch_pair_scalars(s, st));
+            }
+            if (g_profiling) HIPCHK(hipEventRecord(fev[2 * b], st));
+            HIPCHK(launch_flush(s, st));
+            if (g_profiling) HIPCHK(hipEventRecord(fev[2 * b + 1], st));
+            if (use_graph) {
+                HIPCHK(hipGraphLaunch(gr.eb, st));
+            } else {
+                HIPCHK(launch_block_finalize(s, st));
+                HIPCHK(launch_switch_vectors(s, st));
+            }
+            ++blocks;
         }
-        HIPCHK(launch_pair_scalars(s, st));
-        if (g_profiling) HIPCHK(hipEventRecord(fe0, st));
-        HIPCHK(launch_flush(s, st));
-        if (g_profiling) HIPCHK(hipEventRecord(fe1, st));
-        HIPCHK(launch_block_finalize(s, st));
-        HIPCHK(launch_switch_vectors(s, st));
         HIPCHK(hipMemcpyAsync(hs, s.seed, K * sizeof(SeedState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        ++blocks;
         if (g_profiling) {
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, fe0, fe1));
-            g_timing.update_ms += ms;
-            g_timing.update_launches += 1;
+            for (int b = 0; b < per_sync; ++b) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, fev[2 * b], fev[2 * b + 1]));
+                g_timing.update_ms += ms;
+                g_timing.update_launches += 1;
+            }
         }
         done = true;
         for (int64_t j = 0; j < K; ++j)

@@ -30,6 +30,13 @@ __device__ inline float2 cfma(float2 a, float2 b, float2 c)
 __device__ inline double rfma(double a, double b, double c) { return fma(a, b, c); }
 __device__ inline float rfma(float a, float b, float c) { return fmaf(a, b, c); }
 
+template <typename V>
+__device__ inline V to_v(double2 a);
+template <>
+__device__ inline double2 to_v<double2>(double2 a) { return a; }
+template <>
+__device__ inline float2 to_v<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+
 // ---------------------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------------------
@@ -154,6 +161,7 @@ __global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restri
         st.a0 = cmk(1, 0);
         st.b0 = cmk(0, 0);
         st.inv_pt = cmk(1, 0);
+        st.inv_ppt = cmk(1, 0);
         st.nb = nb;
         st.rnorm = nb;
         st.seed = sd;
@@ -311,9 +319,16 @@ __global__ void __launch_bounds__(WG) k_r_update(SolveDev s)
 // shift scalars for the steps of the finished block (one thread per (rhs, shift) pair):
 //   pi_{n+1} = (1 + alpha_n sigma) pi_n + (alpha_n beta_{n-1} / alpha_{n-1}) (pi_n - pi_{n-1})
 //   alpha^k_n = (pi_n / pi_{n+1}) alpha_n,  beta^k_n = (pi_n / pi_{n+1})^2 beta_n
-// and the coefficients of the deferred vector update of step n:
-//   (alpha^k_n, beta^k_{n-1}, 1 / pi_n).  Convergence: ||r_{n+1}|| / (|pi_{n+1}| ||b||) < tol.
+// Convergence of the pair: ||r_{n+1}|| / (|pi_{n+1}| ||b||) < tol.
+//
+// The vector update is carried out on the scaled direction u^k_n = pi_n p^k_n, for which
+//   u^k_n = r_n + b'_n u^k_{n-1},   x^k_{n+1} = x^k_n + a'_n u^k_n,
+//   a'_n = alpha^k_n / pi_n = alpha_n / pi_{n+1},
+//   b'_n = beta^k_{n-1} pi_n / pi_{n-1} = beta_{n-1} pi_{n-1} / pi_n
+// (two complex multiply-adds per step instead of three for p^k directly).  This thread
+// writes (a'_n, b'_n) for every step of the block in which the pair is still active.
 // ---------------------------------------------------------------------------------------
+template <typename V>
 __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
 {
     const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -330,7 +345,7 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
     double2 pi = s.pi[pair], pip = s.pi_prev[pair], bk = s.beta_k[pair];
     double res = s.res[pair];
     int act = 1, status = s.pstatus[pair], na = 0, iters = s.iters[pair];
-    double2 *cf = s.coef + pair * (int64_t)s.TB * 3;
+    V *cf = (V *)s.coef + pair * (int64_t)s.TB * 2;
     for (int t = 0; t < ns; ++t) {
         const double2 a = s.ahist[j * s.TB + t];
         const double2 b = s.bhist[j * s.TB + t];
@@ -343,9 +358,8 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
             break;
         }
         const double2 ratio = cdiv(pi, pin);
-        cf[3 * t + 0] = cmul(ratio, a);
-        cf[3 * t + 1] = bk;
-        cf[3 * t + 2] = cdiv(cmk(1, 0), pi);
+        cf[2 * t + 0] = to_v<V>(cdiv(a, pin));
+        cf[2 * t + 1] = to_v<V>(cmul(bp, cdiv(pip, pi)));
         bk = cmul(cmul(ratio, ratio), b);
         pip = pi;
         pi = pin;
@@ -369,7 +383,7 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
     s.active[pair] = act;
     s.nact[pair] = na;
     if (na > 0) {
-        // algorithmic bytes of this pair's deferred update: p_k (and x_k unless projected)
+        // algorithmic bytes of this pair's deferred update: u_k (and x_k unless projected)
         // written once, and read once unless this is the first block
         const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;
         const unsigned long long nv = s.X ? 2ull : 1ull;
@@ -380,89 +394,103 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
 }
 
 // ---------------------------------------------------------------------------------------
-// Deferred per-shift update: for each active pair and each step t < nact of the block
-//   p_k <- r_t / pi + beta^k p_k ;  x_k <- x_k + alpha^k p_k
-// x_k and p_k stay in registers across the block, so they are read and written once per
+// Deferred per-shift update.  For every active pair and every step t < nact of the block
+//   u_k <- r_t + b'_t u_k ;  x_k <- x_k + a'_t u_k
+// x_k and u_k stay in registers across the block, so each is read and written once per
 // block instead of once per iteration.  One thread per row; a workgroup covers 256 rows of
-// one rhs and `shifts_per_wg` shifts; coefficients are uniform across the workgroup.
+// one rhs and `G` shifts, NP pairs in flight per thread.  Coefficients and step counts are
+// uniform across the workgroup (scalar loads).  x_k and u_k are streamed with nontemporal
+// loads and stores: they are not reused before the next block.
 // ---------------------------------------------------------------------------------------
-template <int TB, typename S>
-struct StoreT;
-template <int TB>
-struct StoreT<TB, double2> {
-    typedef double2 V;
-    typedef double R;
-};
-template <int TB>
-struct StoreT<TB, float2> {
-    typedef float2 V;
-    typedef float R;
-};
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
-template <typename V>
-__device__ inline V to_v(double2 a);
-template <>
-__device__ inline double2 to_v<double2>(double2 a) { return a; }
-template <>
-__device__ inline float2 to_v<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+__device__ inline double2 ld_nt(const double2 *p)
+{
+    const d2v v = __builtin_nontemporal_load((const d2v *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ inline float2 ld_nt(const float2 *p)
+{
+    const f2v v = __builtin_nontemporal_load((const f2v *)p);
+    return make_float2(v.x, v.y);
+}
+__device__ inline void st_nt(double2 *p, double2 v)
+{
+    const d2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (d2v *)p);
+}
+__device__ inline void st_nt(float2 *p, float2 v)
+{
+    const f2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (f2v *)p);
+}
 
-template <int TB, typename V>
-__global__ void __launch_bounds__(WG) k_flush(SolveDev s, int ngroups)
+template <int TB, typename V, int NP, bool PROJ>
+__global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed, const double2 *__restrict__ ring,
+                                              const V *__restrict__ coef, const int32_t *__restrict__ nact,
+                                              V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
+                                              const int64_t *__restrict__ proj_row, int64_t n, int64_t K, int64_t M,
+                                              int G, int ngroups)
 {
     const int64_t j = blockIdx.y / ngroups;
     const int g = blockIdx.y % ngroups;
-    const SeedState st = s.seed[j];
-    const int ns = st.step;
+    const int ns = seed[j].step;
     if (ns == 0) return;
+    const int base = seed[j].base;
+    const bool fresh = seed[j].iter == ns;
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (row >= s.n) return;
-    const bool fresh = (st.iter - ns) == 0;
+    if (row >= n) return;
     V r[TB];
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
-        if (t < ns) r[t] = to_v<V>(ring_slot(s, (st.base + t) % (TB + 1), j)[row]);
+        if (t < ns) r[t] = to_v<V>(ring[((int64_t)((base + t) % (TB + 1)) * K + j) * n + row]);
         else r[t] = to_v<V>(cmk(0, 0));
     }
-    const int G = s.shifts_per_wg;
     const int64_t k0 = (int64_t)g * G;
-    const int64_t k1 = min(k0 + G, s.M);
-    V *X = (V *)s.X;
-    V *P = (V *)s.P;
-    const int64_t prow = s.Xproj ? s.proj_row[j] : -1;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int64_t pair = j * s.M + k;
-        const int na = s.nact[pair];
-        if (na == 0) continue;
-        const int64_t idx = pair * s.n + row;
-        V x, p;
-        if (fresh) {
-            x = to_v<V>(cmk(0, 0));
-            p = x;
-        } else {
-            p = P[idx];
-            if (X) x = X[idx];
-            else x = (row == prow) ? to_v<V>(s.Xproj[pair]) : to_v<V>(cmk(0, 0));
-        }
-        const double2 *cf = s.coef + pair * (int64_t)TB * 3;
+    const int64_t k1 = min(k0 + G, M);
+    const int64_t prow = PROJ ? proj_row[j] : -1;
+    for (int64_t k = k0; k < k1; k += NP) {
+        V x[NP], u[NP];
+        int na[NP];
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            if (t < na) {
-                const V a = to_v<V>(cf[3 * t + 0]);
-                const V b = to_v<V>(cf[3 * t + 1]);
-                const V c = to_v<V>(cf[3 * t + 2]);
-                // p = c r_t + b p ;  x = x + a p
-                V bp;
-                bp.x = b.x * p.x;
-                bp.y = b.x * p.y;
-                bp.x = rfma(-b.y, p.y, bp.x);
-                bp.y = rfma(b.y, p.x, bp.y);
-                p = cfma(c, r[t], bp);
-                x = cfma(a, p, x);
+        for (int q = 0; q < NP; ++q) {
+            const int64_t pair = j * M + k + q;
+            na[q] = (k + q < k1) ? nact[pair] : 0;
+            x[q] = to_v<V>(cmk(0, 0));
+            u[q] = x[q];
+            if (na[q] > 0 && !fresh) {
+                u[q] = ld_nt(P + pair * n + row);
+                if (PROJ) {
+                    if (row == prow) x[q] = to_v<V>(Xproj[pair]);
+                } else {
+                    x[q] = ld_nt(X + pair * n + row);
+                }
             }
         }
-        P[idx] = p;
-        if (X) X[idx] = x;
-        else if (row == prow) s.Xproj[pair] = make_double2((double)x.x, (double)x.y);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                if (t < na[q]) {
+                    const V *cf = coef + ((j * M + k + q) * TB + t) * 2;
+                    u[q] = cfma(cf[1], u[q], r[t]);
+                    x[q] = cfma(cf[0], u[q], x[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int64_t pair = j * M + k + q;
+            if (na[q] > 0) {
+                st_nt(P + pair * n + row, u[q]);
+                if (PROJ) {
+                    if (row == prow) Xproj[pair] = make_double2((double)x[q].x, (double)x[q].y);
+                } else {
+                    st_nt(X + pair * n + row, x[q]);
+                }
+            }
+        }
     }
 }
 
@@ -574,12 +602,15 @@ __global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
         w->zs = s.z[t];
         w->seed = t;
         w->inv_pt = cdiv(cmk(1, 0), pt);
+        w->inv_ppt = cdiv(cmk(1, 0), ppt);
         w->sw_target = t;
         w->switches = st.switches + 1;
     }
 }
 
-// r <- r / pi_t, p <- p_t (the new seed's direction), rho <- r.r
+// Vectors of a seed switch to shift t after step n: r <- r / pi_t(n+1); the stored scaled
+// directions of the active pairs move to the new seed's scale, u_k <- u_k / pi_t(n); the new
+// seed's direction is p <- p_t(n) = u_t / pi_t(n); rho <- r.r.
 template <typename V>
 __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
 {
@@ -593,8 +624,17 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
         double2 *rp = ring_slot(s, st.base, j) + row;
         const double2 r = cmul(*rp, st.inv_pt);
         *rp = r;
-        const V pt = ((const V *)s.P)[(j * s.M + st.sw_target) * s.n + row];
-        s.p[j * s.n + row] = make_double2((double)pt.x, (double)pt.y);
+        V *P = (V *)s.P;
+        const V sc = to_v<V>(st.inv_ppt);
+        const V zero = to_v<V>(cmk(0, 0));
+        for (int64_t k = 0; k < s.M; ++k) {
+            const int64_t pair = j * s.M + k;
+            if (!s.active[pair]) continue;
+            V *up = P + pair * s.n + row;
+            const V u = cfma(sc, *up, zero);
+            *up = u;
+            if (k == st.sw_target) s.p[j * s.n + row] = make_double2((double)u.x, (double)u.y);
+        }
         rr = cmul(r, r);
     }
     rr = block_sum2(rr, sh2);
@@ -824,18 +864,33 @@ hipError_t launch_r_update(const SolveDev &s, hipStream_t st)
 hipError_t launch_pair_scalars(const SolveDev &s, hipStream_t st)
 {
     const int64_t KM = s.K * s.M;
-    hipLaunchKernelGGL(k_pair_scalars, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, s);
+    const dim3 g((unsigned)((KM + WG - 1) / WG));
+    if (s.precision == 0) hipLaunchKernelGGL(k_pair_scalars<double2>, g, dim3(WG), 0, st, s);
+    else hipLaunchKernelGGL(k_pair_scalars<float2>, g, dim3(WG), 0, st, s);
+    return hipGetLastError();
+}
+
+template <int TB, typename V, int NP>
+static hipError_t flush_v(const SolveDev &s, hipStream_t st)
+{
+    const int G = s.shifts_per_wg;
+    const int ng = (int)((s.M + G - 1) / G);
+    const dim3 g = grid2(s.nblk, s.K * ng);
+    const V *coef = (const V *)s.coef;
+    if (s.Xproj)
+        hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)nullptr,
+                           (V *)s.P, s.Xproj, s.proj_row, s.n, s.K, s.M, G, ng);
+    else
+        hipLaunchKernelGGL((k_flush<TB, V, NP, false>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)s.X,
+                           (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.n, s.K, s.M, G, ng);
     return hipGetLastError();
 }
 
 template <int TB>
 static hipError_t flush_tb(const SolveDev &s, hipStream_t st)
 {
-    const int ng = (int)((s.M + s.shifts_per_wg - 1) / s.shifts_per_wg);
-    const dim3 g = grid2(s.nblk, s.K * ng);
-    if (s.precision == 0) hipLaunchKernelGGL((k_flush<TB, double2>), g, dim3(WG), 0, st, s, ng);
-    else hipLaunchKernelGGL((k_flush<TB, float2>), g, dim3(WG), 0, st, s, ng);
-    return hipGetLastError();
+    if (s.precision == 0) return flush_v<TB, double2, 2>(s, st);
+    return flush_v<TB, float2, 4>(s, st);
 }
 
 hipError_t launch_flush(const SolveDev &s, hipStream_t st)

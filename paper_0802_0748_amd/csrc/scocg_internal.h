@@ -47,7 +47,8 @@ struct SeedState {
     double2 beta_prev;   // beta_{n-1}
     double2 rho;         // r.r (unconjugated)
     double2 a0, b0;      // alpha_{n0-1}, beta_{n0-1} at the start of the current block
-    double2 inv_pt;      // 1 / pi_t of a pending seed switch
+    double2 inv_pt;      // 1 / pi_t(n+1) of a pending seed switch (scales r)
+    double2 inv_ppt;     // 1 / pi_t(n) of a pending seed switch (scales the stored directions)
     double nb;           // ||b||
     double rnorm;        // ||r||
     int32_t seed;        // seed shift index
@@ -96,7 +97,8 @@ struct SolveDev {
     SeedState *seed;           // [K]
     double2 *ring;             // [(TB+1)][K][n]
     double2 *p, *q;            // [K][n]
-    void *X, *P;               // [K][M][n] (double2 or float2); X may be null in projection mode
+    void *X, *P;               // [K][M][n] (double2 or float2); X may be null in projection mode.
+                               // P holds the scaled directions u_k = pi_k p_k (see k_flush)
     double2 *Xproj;            // [K][M] projected solution (projection mode) or null
     const int64_t *proj_row;   // [K] row kept in projection mode
     double2 *pi, *pi_prev, *beta_k; // [K*M]
@@ -104,7 +106,7 @@ struct SolveDev {
     int32_t *iters, *pstatus, *active, *nact; // [K*M]
     double2 *ahist, *bhist;    // [K][TB]
     double *rnhist;            // [K][TB]
-    double2 *coef;             // [K*M][TB][3]
+    void *coef;                // [K*M][TB][2] (a', b') as double2 (FP64) or float2 (FP32 storage)
     double2 *part2;            // [K][nblk] complex partials
     double *part1;             // [K][nblk] real partials
     uint32_t *cnt;             // [K] last-block counters

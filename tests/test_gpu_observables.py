@@ -1,0 +1,161 @@
+"""Density matrix, band energy, backward and autograd through the HIP library,
+against the FP64 oracle, dense references and finite differences."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import diamond, random_sparse_symmetric
+from workloads.lattices import diamond_entry_map, diamond_geometry
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _S():
+    import paper_0802_0748_amd as S
+
+    return S
+
+
+def _contour(H, nq):
+    lo, _ = O.gershgorin(H)
+    return lo - 1.0, 0.0, nq
+
+
+def test_density_matrix_energy_matches_oracle():
+    S = _S()
+    Hc, _ = diamond(1, 1, 1, np.random.default_rng(4))
+    e_lo, mu, nq = _contour(Hc, 48)
+    z, w = S.contour(e_lo, mu, nq)
+    H = S.Hamiltonian.from_csr(Hc)
+    out = S.density_matrix_energy(H, z, w, want_rho=True, want_grad=True, tol=1e-13, max_iter=3000, rhs_batch=7)
+    ref = O.density_matrix_energy(Hc, z, w, tol=1e-13, max_iter=3000)
+    assert abs(out["E"].item() - ref["E"]) < 1e-10 * max(1, abs(ref["E"]))
+    assert np.max(np.abs(out["rho"].cpu().numpy() - ref["rho"])) < 1e-10
+    assert np.max(np.abs(out["grad"].cpu().numpy() - ref["grad"])) < 1e-9 * max(1, np.max(np.abs(ref["grad"])))
+
+
+def test_backward_through_greens_diag_matches_formula():
+    """dL/dH_ab = Re sum conj(g_kj) x_kj[a] x_kj[b], with x from the oracle and random g."""
+    S = _S()
+    rng = np.random.default_rng(1)
+    Hc = random_sparse_symmetric(150, 0.04, rng, diag_scale=2.0)
+    z = np.linspace(-2, 2, 5) + 0.2j
+    idx = np.array([3, 77, 149])
+    H = S.Hamiltonian.from_csr(Hc)
+    G, rep, tape, rc = S.greens_diag(H, z, idx, tol=1e-13, max_iter=3000, keep_tape=True)
+    g = rng.normal(size=(len(z), len(idx))) + 1j * rng.normal(size=(len(z), len(idx)))
+    grad = S.backward(tape, torch.from_numpy(g).cuda()).cpu().numpy()
+    rows = np.repeat(np.arange(Hc.n), np.diff(Hc.row_ptr))
+    ref = np.zeros(Hc.nnz)
+    for c, j in enumerate(idx):
+        X = O.shifted_cocg(Hc, z, O.unit(Hc.n, j), tol=1e-13, max_iter=3000)["X"]
+        assert np.max(np.abs(G.cpu().numpy()[:, c] - X[:, j])) < 1e-10
+        for k in range(len(z)):
+            ref += np.real(np.conj(g[k, c]) * X[k][rows] * X[k][Hc.col])
+    assert np.max(np.abs(grad - ref)) < 1e-9 * max(1, np.max(np.abs(ref)))
+
+
+def test_greens_diag_autograd_matches_dense_torch():
+    """torch.autograd through GreensDiag against autograd through a dense complex inverse (CPU)."""
+    S = _S()
+    from paper_0802_0748_amd.autograd import greens_diag
+
+    rng = np.random.default_rng(2)
+    Hc = random_sparse_symmetric(60, 0.08, rng, diag_scale=2.0)
+    z = np.linspace(-1.5, 1.5, 4) + 0.3j
+    idx = np.array([0, 17, 59])
+    H = S.Hamiltonian.from_csr(Hc)
+    vals = torch.tensor(Hc.val, dtype=torch.float64, requires_grad=True)
+    G = greens_diag(vals, H, z, idx, tol=1e-13, max_iter=3000)
+    wgt = torch.from_numpy(rng.normal(size=G.shape) + 1j * rng.normal(size=G.shape)).cuda()
+    loss = (torch.abs(G) ** 2).sum() + torch.real(wgt * G).sum()
+    loss.backward()
+    # dense reference on the CPU
+    rows = torch.from_numpy(np.repeat(np.arange(Hc.n), np.diff(Hc.row_ptr)))
+    cols = torch.from_numpy(Hc.col)
+    v2 = torch.tensor(Hc.val, dtype=torch.float64, requires_grad=True)
+    A = torch.zeros((Hc.n, Hc.n), dtype=torch.float64).index_put((rows, cols), v2)
+    Gs = []
+    for zk in z:
+        Ginv = torch.linalg.inv(zk * torch.eye(Hc.n, dtype=torch.complex128) - A.to(torch.complex128))
+        Gs.append(Ginv[idx, idx])
+    Gd = torch.stack(Gs)
+    assert torch.max(torch.abs(Gd - G.detach().cpu())) < 1e-10
+    loss_d = (torch.abs(Gd) ** 2).sum() + torch.real(wgt.cpu() * Gd).sum()
+    loss_d.backward()
+    assert torch.max(torch.abs(vals.grad - v2.grad)) < 1e-8 * max(1.0, torch.max(torch.abs(v2.grad)).item())
+
+
+def _diamond_model(cells, seed):
+    Hc, geo = diamond(*cells, np.random.default_rng(seed))
+    kind, bond, o1, o2 = diamond_entry_map(Hc, geo["bonds"])
+    _, bonds, vec0 = diamond_geometry(*cells)
+    t = lambda a: torch.from_numpy(np.asarray(a))
+    model = dict(vec0=t(vec0), bonds=t(bonds), blocks=t(geo["blocks"]), kind=t(kind), bond=t(bond), o1=t(o1),
+                 o2=t(o2), onsite=t(Hc.val.copy()))
+    return Hc, geo, model
+
+
+def _values(model, disp):
+    from paper_0802_0748_amd.autograd import hopping_values
+
+    m = model
+    return hopping_values(m["vec0"], disp, m["bonds"], m["blocks"], m["kind"], m["bond"], m["o1"], m["o2"],
+                          m["onsite"])
+
+
+def test_band_energy_forces_match_finite_differences():
+    """Forces -dE/dR through t(r) = exp(-2 (r - r0)) on the 32-atom cell, against central
+    differences (h = 1e-5) of the GPU band energy with the contour held fixed."""
+    S = _S()
+    from paper_0802_0748_amd.autograd import band_energy
+
+    Hc, geo, model = _diamond_model((2, 2, 1), 0)
+    e_lo, mu, nq = _contour(Hc, 128)
+    z, w = S.contour(e_lo - 2.0, mu, nq)
+    H = S.Hamiltonian.from_csr(Hc)
+    disp0 = torch.from_numpy(geo["displacement"].copy())
+    disp = disp0.clone().requires_grad_(True)
+    E = band_energy(_values(model, disp), H, z, w, tol=1e-13, max_iter=5000)
+    E.backward()
+    forces = -disp.grad.numpy()
+    h = 1e-5
+    rng = np.random.default_rng(0)
+    for a, c in [(0, 0), (5, 1), (17, 2), (31, 0), (int(rng.integers(32)), int(rng.integers(3)))]:
+        Es = []
+        for sgn in (+1, -1):
+            d = disp0.clone()
+            d[a, c] += sgn * h
+            Es.append(band_energy(_values(model, d), H, z, w, tol=1e-13, max_iter=5000).item())
+        fd = -(Es[0] - Es[1]) / (2 * h)
+        assert abs(fd - forces[a, c]) < 1e-6 * max(1.0, abs(forces[a, c])), (a, c, fd, forces[a, c])
+
+
+def test_band_energy_gradient_matches_dense_autograd():
+    """dE/dR on the 64-atom cell against FP64 torch autograd through dense complex inverses."""
+    S = _S()
+    from paper_0802_0748_amd.autograd import band_energy
+
+    Hc, geo, model = _diamond_model((2, 2, 2), 3)
+    e_lo, mu, nq = _contour(Hc, 64)
+    z, w = S.contour(e_lo - 2.0, mu, nq)
+    H = S.Hamiltonian.from_csr(Hc)
+    disp = torch.from_numpy(geo["displacement"].copy()).requires_grad_(True)
+    E = band_energy(_values(model, disp), H, z, w, tol=1e-13, max_iter=5000)
+    E.backward()
+    g_gpu = disp.grad.clone()
+    d2 = torch.from_numpy(geo["displacement"].copy()).requires_grad_(True)
+    vals = _values(model, d2)
+    rows = torch.from_numpy(np.repeat(np.arange(Hc.n), np.diff(Hc.row_ptr)))
+    A = torch.zeros((Hc.n, Hc.n), dtype=torch.float64).index_put((rows, torch.from_numpy(Hc.col)), vals)
+    Ac = A.to(torch.complex128)
+    I = torch.eye(Hc.n, dtype=torch.complex128)
+    Ed = 0.0
+    for zk, wk in zip(z, w):
+        G = torch.linalg.inv(zk * I - Ac)
+        Ed = Ed + torch.real(wk * zk * torch.diagonal(G).sum())
+    assert abs(Ed.item() - E.item()) < 1e-9 * max(1.0, abs(Ed.item()))
+    Ed.backward()
+    assert torch.max(torch.abs(g_gpu - d2.grad)) < 1e-8 * max(1.0, torch.max(torch.abs(d2.grad)).item())

@@ -101,6 +101,41 @@ def diamond_hamiltonian(nx, ny, nz, displacement, blocks, onsite=(-5.0, 1.0, 1.0
     return H, dict(positions=pos + displacement, bonds=bonds, bond_vec=dvec, bond_len=r, scale=s)
 
 
+def diamond_entry_map(H: CSR, bonds: np.ndarray):
+    """Where every stored entry of a diamond Hamiltonian comes from.
+
+    Returns (kind, bond, o1, o2): kind 0 = on-site diagonal, 1 = element B[o1, o2] of the
+    hopping block of bond `bond` (entry in the a-row, b-column block, a < b), 2 = the
+    mirrored entry, whose value is the same block element B[o1, o2] (indices already
+    swapped so that both kinds read blocks[bond, o1, o2]).
+    """
+    rows = np.repeat(np.arange(H.n), np.diff(H.row_ptr))
+    cols = H.col
+    natom = H.n // 4
+    lookup = {}
+    for k, (a, b) in enumerate(bonds):
+        lookup[(int(a), int(b))] = k
+    kind = np.zeros(H.nnz, dtype=np.int64)
+    bond = np.zeros(H.nnz, dtype=np.int64)
+    o1 = np.zeros(H.nnz, dtype=np.int64)
+    o2 = np.zeros(H.nnz, dtype=np.int64)
+    ra, rb = rows // 4, cols // 4
+    for e in range(H.nnz):
+        a, b = int(ra[e]), int(rb[e])
+        if rows[e] == cols[e]:
+            continue
+        if a < b:
+            kind[e] = 1
+            bond[e] = lookup[(a, b)]
+            o1[e], o2[e] = rows[e] % 4, cols[e] % 4
+        else:
+            kind[e] = 2
+            bond[e] = lookup[(b, a)]
+            o1[e], o2[e] = cols[e] % 4, rows[e] % 4
+    assert natom * 4 == H.n
+    return kind, bond, o1, o2
+
+
 def diamond(nx: int, ny: int, nz: int, rng: np.random.Generator, sigma: float = 0.02):
     """Seeded diamond instance: displacements N(0, sigma), blocks U[-2,2]."""
     pos, bonds, _ = diamond_geometry(nx, ny, nz)
