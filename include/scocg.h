@@ -60,7 +60,10 @@ typedef struct {
     int32_t check_true;     /* 1: compute the FP64 true residual of every pair into the report */
     int32_t keep_tape;      /* 1: keep the solutions for backward() */
     int32_t no_graph;       /* 1: launch every kernel directly instead of replaying captured HIP graphs */
-    int32_t reserved[5];
+    int32_t refine;         /* sweeps of FP64 refinement for pairs whose true residual exceeds tol: each solves
+                               (z_k - H) d = b - (z_k - H) x per pair (COCG, FP64 vectors) and adds d to x.
+                               Needs full solutions (shifted_cocg_solve); implies check_true. */
+    int32_t reserved[4];
 } scocg_opts;
 
 typedef struct {
@@ -122,6 +125,23 @@ int shifted_cocg_solve(scocg_csr_t H, int64_t n_shift, const double *z, int64_t 
  */
 int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,
                 const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream);
+
+/*
+ * G_jj(z_k) for several Hamiltonians of different sizes in one solve (a batch of
+ * independent problems sharing the shift list).  Problem q has n_rhs[q] unit
+ * right-hand sides; rhs_idx lists them problem after problem (indices local to the
+ * problem's rows).  Every right-hand side iterates its own seed on its own matrix
+ * and retires on its own; all of them advance in the same kernel launches.
+ *   H       host array of n_problems uploaded matrices
+ *   G       device, [n_shift][sum n_rhs] complex output (columns in rhs_idx order)
+ *   rep     host, [sum n_rhs][n_shift] reports, or NULL
+ * Device memory: the directions of every (rhs, shift) pair are stored in full,
+ * n_shift * sum_q n_rhs[q] * n_q complex numbers (8 or 16 bytes each); callers
+ * split larger batches into waves that fit.
+ */
+int greens_diag_batched(int64_t n_problems, const scocg_csr_t *H, const int64_t *n_rhs, const int64_t *rhs_idx,
+                        int64_t n_shift, const double *z, const scocg_opts *o, double *G, scocg_pair_report *rep,
+                        void *stream);
 
 /*
  * Density matrix and band energy at zero temperature from a contour integral of

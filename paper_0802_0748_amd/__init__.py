@@ -6,6 +6,7 @@ PyTorch used for device memory, streams and autograd.
 """
 
 from .api import (Hamiltonian, Tape, backward, contour, csr_validate, density_matrix_energy, greens_diag,
+                  greens_diag_batched, greens_diag_waves,
                   last_timing, options, set_profiling, shifted_cocg_solve)
 
 __all__ = [
@@ -16,6 +17,8 @@ __all__ = [
     "csr_validate",
     "density_matrix_energy",
     "greens_diag",
+    "greens_diag_batched",
+    "greens_diag_waves",
     "last_timing",
     "options",
     "set_profiling",

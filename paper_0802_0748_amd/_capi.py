@@ -28,7 +28,8 @@ class Opts(ctypes.Structure):
         ("check_true", ctypes.c_int32),
         ("keep_tape", ctypes.c_int32),
         ("no_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("refine", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -63,6 +64,7 @@ EXPORTED = [
     "csr_free",
     "shifted_cocg_solve",
     "greens_diag",
+    "greens_diag_batched",
     "density_matrix_energy",
     "backward",
     "tape_free",
@@ -104,6 +106,8 @@ def load():
     lib.shifted_cocg_solve.restype = i32
     lib.greens_diag.argtypes = [P, i64, P, i64, P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(P), P]
     lib.greens_diag.restype = i32
+    lib.greens_diag_batched.argtypes = [i64, P, P, P, i64, P, ctypes.POINTER(Opts), P, P, P]
+    lib.greens_diag_batched.restype = i32
     lib.density_matrix_energy.argtypes = [P, i64, P, P, i64, P, ctypes.POINTER(Opts), i64, P, P, P, P]
     lib.density_matrix_energy.restype = i32
     lib.backward.argtypes = [P, P, P, P]

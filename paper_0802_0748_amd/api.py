@@ -22,7 +22,7 @@ def _require_gpu():
 
 
 def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switching=True, fixed_iter=0, block=0,
-            shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False) -> C.Opts:
+            shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False, refine=0) -> C.Opts:
     o = C.Opts()
     C.load().scocg_default_opts(ctypes.byref(o))
     o.tol = float(tol)
@@ -36,6 +36,7 @@ def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switc
     o.check_true = int(bool(check_true))
     o.keep_tape = int(bool(keep_tape))
     o.no_graph = int(bool(no_graph))
+    o.refine = int(refine)
     return o
 
 
@@ -187,6 +188,55 @@ def greens_diag(H: Hamiltonian, z, rhs_idx, allow_noconv=True, allow_breakdown=F
     C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
     t = Tape(tape, "greens", M, K, H.nnz) if o.keep_tape and tape.value else None
     return G, _report(rep, K, M), t, rc
+
+
+def greens_diag_batched(Hs, z, rhs_lists, allow_noconv=True, allow_breakdown=False, **opts):
+    """G_jj(z_k) for several Hamiltonians of different sizes in one solve.
+
+    Hs: list of Hamiltonian; rhs_lists: per problem, the row indices j of its unit
+    right-hand sides.  Returns (list of G_q [n_shift, len(rhs_lists[q])], list of reports, rc).
+    """
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    counts = np.array([len(r) for r in rhs_lists], dtype=np.int64)
+    idx = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.int64) for r in rhs_lists]))
+    handles = (ctypes.c_void_p * len(Hs))(*[H.handle.value for H in Hs])
+    K, M = int(counts.sum()), len(zh)
+    G = torch.empty((M, K), dtype=torch.complex128, device=torch.device("cuda"))
+    o = options(**opts)
+    rep = (C.PairReport * (K * M))()
+    rc = lib.greens_diag_batched(len(Hs), handles, counts.ctypes.data, idx.ctypes.data, M, zp, ctypes.byref(o),
+                                 G.data_ptr(), rep, _stream_ptr())
+    C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
+    full = _report(rep, K, M)
+    bounds = np.concatenate([[0], np.cumsum(counts)])
+    Gs = [G[:, bounds[q]:bounds[q + 1]] for q in range(len(Hs))]
+    reps = [{k: v[bounds[q]:bounds[q + 1]] for k, v in full.items()} for q in range(len(Hs))]
+    return Gs, reps, rc
+
+
+def greens_diag_waves(Hs, z, rhs_lists, max_bytes=64e9, **opts):
+    """greens_diag_batched over waves of problems whose stored directions fit in max_bytes."""
+    esz = 8 if opts.get("precision", "fp64") in ("fp32", 1) else 16
+    M = len(z)
+    waves, cur, cur_bytes = [], [], 0.0
+    for q, (H, r) in enumerate(zip(Hs, rhs_lists)):
+        b = esz * M * len(r) * H.n
+        if cur and cur_bytes + b > max_bytes:
+            waves.append(cur)
+            cur, cur_bytes = [], 0.0
+        cur.append(q)
+        cur_bytes += b
+    if cur:
+        waves.append(cur)
+    Gs, reps, rcs = [None] * len(Hs), [None] * len(Hs), []
+    for w in waves:
+        g, rp, rc = greens_diag_batched([Hs[q] for q in w], z, [rhs_lists[q] for q in w], **opts)
+        for i, q in enumerate(w):
+            Gs[q], reps[q] = g[i], rp[i]
+        rcs.append(rc)
+    return Gs, reps, max(rcs), waves
 
 
 def contour(e_lo: float, mu: float, n_quad: int):

@@ -299,7 +299,8 @@ int default_seed(const double *z, int64_t M, double centre)
 }
 
 struct SolveRequest {
-    scocg_csr *H;
+    scocg_csr *H;                  // matrix of every rhs, unless Hj is given
+    std::vector<scocg_csr *> Hj;   // matrix per rhs (a batch of uneven Hamiltonians), or empty
     int64_t M, K;
     const double *z;          // host [M] complex
     const double2 *B;         // device [K][n] or null (unit vectors)
@@ -310,38 +311,58 @@ struct SolveRequest {
     double2 *Gout;            // device [M][K] or null
     scocg_pair_report *rep;
     DevBuf *keepX;            // receives the full FP64 solutions (tape) or null
+    bool zper;                // z has one shift per rhs (n_shift = 1): used by the refinement solves
 };
 
 int solve(SolveRequest &rq, hipStream_t st)
 {
-    scocg_csr *Hh = rq.H;
-    const DevCSR &H = Hh->d;
-    const int64_t n = H.n, K = rq.K, M = rq.M;
-    const scocg_opts &o = rq.o;
+    const int64_t K = rq.K, M = rq.M;
     if (M <= 0 || K <= 0) return fail(SCOCG_EINVAL, "n_shift and n_rhs must be positive");
+    if (!rq.Hj.empty() && (int64_t)rq.Hj.size() != K) return fail(SCOCG_EINVAL, "one matrix per rhs expected");
+    // per-rhs matrices and vector offsets
+    std::vector<RhsDesc> hdesc(K);
+    std::vector<double> centre(K);
+    int64_t ntot = 0, n = 0;
+    bool uniform = true;
+    for (int64_t j = 0; j < K; ++j) {
+        const DevCSR &d = (rq.Hj.empty() ? rq.H : rq.Hj[j])->d;
+        hdesc[j] = RhsDesc{d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.nslices, d.n, ntot, 0};
+        centre[j] = d.trace / (double)d.n;
+        ntot += d.n;
+        n = std::max(n, d.n);
+        if (!rq.Hj.empty() && rq.Hj[j] != rq.Hj[0]) uniform = false;
+    }
+    const scocg_opts &o = rq.o;
     if (M > (1 << 20) || K > 65535) return fail(SCOCG_EINVAL, "too many shifts or right-hand sides");
     if (!(o.tol > 0) && o.fixed_iter <= 0) return fail(SCOCG_EINVAL, "tol must be positive");
     if (o.max_iter <= 0 && o.fixed_iter <= 0) return fail(SCOCG_EINVAL, "max_iter must be positive");
     if (o.precision != 0 && o.precision != 1) return fail(SCOCG_EINVAL, "precision must be 0 or 1");
-    for (int64_t k = 0; k < M; ++k)
+    if (rq.zper && M != 1) return fail(SCOCG_EINVAL, "one shift per rhs needs n_shift = 1");
+    const int64_t nz = rq.zper ? K : M;
+    for (int64_t k = 0; k < nz; ++k)
         if (!std::isfinite(rq.z[2 * k]) || !std::isfinite(rq.z[2 * k + 1]))
             return fail(SCOCG_EINVAL, "non-finite shift");
     int TB = o.block > 0 ? o.block : 8;
     if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16)
         return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8 or 16");
     int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 32);
-    int seed0;
-    if (o.seed_index >= 0) {
-        if (o.seed_index >= M) return fail(SCOCG_EINVAL, "seed_index out of range");
-        seed0 = o.seed_index;
-    } else {
-        seed0 = default_seed(rq.z, M, H.trace / (double)n);
+    std::vector<int32_t> seeds(K, 0);
+    for (int64_t j = 0; j < K; ++j) {
+        if (rq.zper) {
+            seeds[j] = (int32_t)j;
+        } else if (o.seed_index >= 0) {
+            if (o.seed_index >= M) return fail(SCOCG_EINVAL, "seed_index out of range");
+            seeds[j] = o.seed_index;
+        } else {
+            seeds[j] = default_seed(rq.z, M, centre[j]);
+        }
     }
+    if (o.refine > 0 && !uniform) return fail(SCOCG_EINVAL, "refinement needs a single matrix");
     const bool fixed = o.fixed_iter > 0;
     const int32_t limit = fixed ? o.fixed_iter : o.max_iter;
     const bool need_full = !rq.projection;
     const size_t KM = (size_t)K * M;
-    const size_t vec = (size_t)K * n;
+    const size_t vec = (size_t)ntot;
     const size_t esz = o.precision == 0 ? sizeof(double2) : sizeof(float2);
 
     g_timing = scocg_timing{};
@@ -359,6 +380,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     HIPCHK(hipEventRecord(ev_t0, st));
 
     SolveDev s{};
+    s.ntot = ntot;
     s.n = n;
     s.K = K;
     s.M = M;
@@ -369,9 +391,10 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.tol = o.tol;
     s.nblk = (n + 255) / 256;
     s.shifts_per_wg = G;
+    s.zper = rq.zper ? 1 : 0;
 
     DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
-        brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats;
+        brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc;
     auto A = [&](DevBuf &b, size_t bytes) -> hipError_t { return b.alloc(bytes); };
     hipError_t e = hipSuccess;
 #define ALLOC(buf, bytes)                                                                                  \
@@ -381,14 +404,15 @@ int solve(SolveRequest &rq, hipStream_t st)
             return fail(SCOCG_ENOMEM, std::string("device allocation of ") + std::to_string((size_t)(bytes)) + \
                                           " bytes failed: " + hipGetErrorString(e));                      \
     } while (0)
-    ALLOC(bz, M * sizeof(double2));
+    ALLOC(bz, nz * sizeof(double2));
     ALLOC(bseed, K * sizeof(SeedState));
     ALLOC(bring, (size_t)(TB + 1) * vec * sizeof(double2));
     ALLOC(bp, vec * sizeof(double2));
     ALLOC(bq, vec * sizeof(double2));
-    ALLOC(bP, KM * n * esz);
+    ALLOC(bP, (size_t)M * ntot * esz);
     const bool x_is_out = need_full && o.precision == 0 && rq.Xout && !rq.keepX;
-    if (need_full && !x_is_out) ALLOC(bX, KM * n * esz);
+    if (need_full && !x_is_out) ALLOC(bX, (size_t)M * ntot * esz);
+    ALLOC(bdesc, K * sizeof(RhsDesc));
     if (!need_full) {
         ALLOC(bXproj, KM * sizeof(double2));
         ALLOC(bprow, K * sizeof(int64_t));
@@ -437,9 +461,10 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.part1 = bp1.as<double>();
     s.cnt = bcnt.as<uint32_t>();
     s.stats = bstats.as<unsigned long long>();
+    s.desc = bdesc.as<RhsDesc>();
 
-    std::vector<int32_t> seeds(K, seed0);
-    HIPCHK(hipMemcpyAsync(bz.ptr, rq.z, M * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bdesc.ptr, hdesc.data(), K * sizeof(RhsDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bz.ptr, rq.z, nz * sizeof(double2), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bsd.ptr, seeds.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
     if (rq.unit_idx) {
         HIPCHK(hipMemcpyAsync(bidx.ptr, rq.unit_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -447,8 +472,8 @@ int solve(SolveRequest &rq, hipStream_t st)
     }
     HIPCHK(launch_zero(bcnt.ptr, K * sizeof(uint32_t), st));
     HIPCHK(launch_zero(bstats.ptr, 2 * sizeof(unsigned long long), st));
-    if (need_full) HIPCHK(launch_zero(s.X, KM * n * esz, st));
-    HIPCHK(launch_init(s, H, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, bsd.as<int32_t>(), limit, st));
+    if (need_full) HIPCHK(launch_zero(s.X, (size_t)M * ntot * esz, st));
+    HIPCHK(launch_init(s, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, bsd.as<int32_t>(), limit, st));
 
     PinnedBuf host_state;
     HIPCHK(host_state.alloc(K * sizeof(SeedState)));
@@ -481,7 +506,7 @@ int solve(SolveRequest &rq, hipStream_t st)
         HIPCHK(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
         for (int t = 0; t < TB; ++t) {
             HIPCHK(launch_p_update(s, gr.cap));
-            HIPCHK(launch_spmv(s, H, gr.cap));
+            HIPCHK(launch_spmv(s,gr.cap));
             HIPCHK(launch_r_update(s, gr.cap));
         }
         HIPCHK(launch_pair_scalars(s, gr.cap));
@@ -507,7 +532,7 @@ int solve(SolveRequest &rq, hipStream_t st)
             } else {
                 for (int t = 0; t < TB; ++t) {
                     HIPCHK(launch_p_update(s, st));
-                    HIPCHK(launch_spmv(s, H, st));
+                    HIPCHK(launch_spmv(s,st));
                     HIPCHK(launch_r_update(s, st));
                 }
                 HIPCHK(launch_pair_scalars(s, st));
@@ -547,12 +572,12 @@ int solve(SolveRequest &rq, hipStream_t st)
     // outputs
     if (need_full && rq.Xout && !x_is_out) {
         if (o.precision == 1) HIPCHK(launch_store_solution(s, rq.Xout, st));
-        else HIPCHK(hipMemcpyAsync(rq.Xout, s.X, KM * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        else HIPCHK(hipMemcpyAsync(rq.Xout, s.X, (size_t)M * ntot * sizeof(double2), hipMemcpyDeviceToDevice, st));
     }
     if (rq.keepX) {
-        HIPCHK(rq.keepX->alloc(KM * n * sizeof(double2)) == hipSuccess ? hipSuccess : hipErrorOutOfMemory);
+        HIPCHK(rq.keepX->alloc((size_t)M * ntot * sizeof(double2)) == hipSuccess ? hipSuccess : hipErrorOutOfMemory);
         if (o.precision == 1) HIPCHK(launch_store_solution(s, rq.keepX->as<double2>(), st));
-        else HIPCHK(hipMemcpyAsync(rq.keepX->ptr, s.X, KM * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        else HIPCHK(hipMemcpyAsync(rq.keepX->ptr, s.X, (size_t)M * ntot * sizeof(double2), hipMemcpyDeviceToDevice, st));
     }
     if (rq.Gout) {
         // gather from full FP64 storage (or the projection)
@@ -583,22 +608,86 @@ int solve(SolveRequest &rq, hipStream_t st)
     g_timing.blocks = blocks;
     g_timing.switches = switches;
 
-    if (o.check_true && need_full) {
-        const double2 *X64 = nullptr;
-        DevBuf tmp;
-        if (o.precision == 0) X64 = (const double2 *)s.X;
+    // FP64 true residuals (Sec. 3.4 eq. residual) and, on request, refinement of the pairs whose
+    // true residual misses the tolerance: (z_k - H) d = r_true solved per pair (one shift per
+    // right-hand side, FP64 storage), x <- x + d.
+    double2 *X64 = nullptr;
+    if (need_full) {
+        if (o.precision == 0) X64 = (double2 *)s.X;
         else if (rq.Xout) X64 = rq.Xout;
         else if (rq.keepX) X64 = rq.keepX->as<double2>();
-        if (X64) {
-            DevBuf part, outr;
-            const int64_t gx = (H.nslices + 3) / 4;
-            ALLOC(part, KM * gx * sizeof(double));
-            ALLOC(outr, KM * sizeof(double));
-            HIPCHK(launch_true_residual(s, H, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, X64,
-                                        part.as<double>(), outr.as<double>(), st));
+    }
+    if ((o.check_true || o.refine > 0) && X64) {
+        const scocg_timing saved = g_timing;
+        const int64_t gx = s.nblk;
+        const int64_t *uidx = rq.unit_idx ? bidx.as<int64_t>() : nullptr;
+        std::vector<double> h_nb(K);
+        for (int64_t j = 0; j < K; ++j) h_nb[j] = hs[j].nb;
+        DevBuf bnb, part, outr;
+        ALLOC(bnb, K * sizeof(double));
+        ALLOC(part, KM * gx * sizeof(double));
+        ALLOC(outr, KM * sizeof(double));
+        HIPCHK(hipMemcpyAsync(bnb.ptr, h_nb.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_residual(s, rq.B,uidx, X64, nullptr, (int64_t)KM, bnb.as<double>(), nullptr,
+                               part.as<double>(), outr.as<double>(), st));
+        HIPCHK(hipMemcpyAsync(h_true.data(), outr.ptr, KM * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int64_t chunk = 1024;
+        for (int sweep = 0; sweep < o.refine; ++sweep) {
+            std::vector<int64_t> fail_pairs;
+            for (size_t p = 0; p < KM; ++p)
+                if (h_true[p] > o.tol && h_st[p] != PAIR_BREAKDOWN) fail_pairs.push_back((int64_t)p);
+            if (fail_pairs.empty()) break;
+            for (size_t c0 = 0; c0 < fail_pairs.size(); c0 += chunk) {
+                const int64_t cnt = std::min<int64_t>(chunk, (int64_t)(fail_pairs.size() - c0));
+                std::vector<double2> zc(cnt);
+                double tol_c = 0.5;
+                for (int64_t c = 0; c < cnt; ++c) {
+                    const int64_t p = fail_pairs[c0 + c];
+                    const int64_t k = rq.zper ? p / M : p % M;
+                    zc[c] = make_double2(rq.z[2 * k], rq.z[2 * k + 1]);
+                    tol_c = std::min(tol_c, 0.5 * o.tol / h_true[p]);
+                }
+                DevBuf bl, R, D, pc, oc;
+                ALLOC(bl, cnt * sizeof(int64_t));
+                ALLOC(R, cnt * n * sizeof(double2));
+                ALLOC(D, cnt * n * sizeof(double2));
+                ALLOC(pc, cnt * gx * sizeof(double));
+                ALLOC(oc, cnt * sizeof(double));
+                HIPCHK(hipMemcpyAsync(bl.ptr, fail_pairs.data() + c0, cnt * sizeof(int64_t), hipMemcpyHostToDevice, st));
+                HIPCHK(launch_residual(s, rq.B,uidx, X64, bl.as<int64_t>(), cnt, bnb.as<double>(),
+                                       R.as<double2>(), pc.as<double>(), oc.as<double>(), st));
+                HIPCHK(hipStreamSynchronize(st));
+                SolveRequest cr{};
+                cr.H = rq.Hj.empty() ? rq.H : rq.Hj[0];
+                cr.M = 1;
+                cr.K = cnt;
+                cr.z = (const double *)zc.data();
+                cr.B = R.as<double2>();
+                cr.o = o;
+                cr.o.tol = tol_c;
+                cr.o.precision = 0;
+                cr.o.fixed_iter = 0;
+                cr.o.seed_index = -1;
+                cr.o.seed_switching = 0;
+                cr.o.check_true = 0;
+                cr.o.refine = 0;
+                cr.o.keep_tape = 0;
+                cr.Xout = D.as<double2>();
+                cr.zper = true;
+                const int rc2 = solve(cr, st);
+                if (rc2 != SCOCG_OK && rc2 != SCOCG_ENOCONV) return rc2;
+                HIPCHK(launch_add_correction(n, bl.as<int64_t>(), cnt, D.as<double2>(), X64, st));
+            }
+            HIPCHK(launch_residual(s, rq.B,uidx, X64, nullptr, (int64_t)KM, bnb.as<double>(),
+                                   nullptr, part.as<double>(), outr.as<double>(), st));
             HIPCHK(hipMemcpyAsync(h_true.data(), outr.ptr, KM * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
         }
+        if (o.refine > 0 && rq.keepX && rq.Xout && X64 == rq.Xout)
+            HIPCHK(hipMemcpyAsync(rq.keepX->ptr, rq.Xout, (size_t)M * ntot * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        g_timing = saved;
     }
     int rc = SCOCG_OK;
     for (size_t p = 0; p < KM; ++p) {
@@ -697,6 +786,40 @@ extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int6
         }
     }
     return rc;
+}
+
+extern "C" int greens_diag_batched(int64_t n_problems, const scocg_csr_t *H, const int64_t *n_rhs,
+                                   const int64_t *rhs_idx, int64_t n_shift, const double *z, const scocg_opts *o,
+                                   double *G, scocg_pair_report *rep, void *stream)
+{
+    g_err.clear();
+    if (n_problems <= 0 || !H || !n_rhs || !rhs_idx || !z || !o || !G) return fail(SCOCG_EINVAL, "null argument");
+    SolveRequest rq{};
+    std::vector<int64_t> idx;
+    for (int64_t q = 0; q < n_problems; ++q) {
+        if (!H[q] || n_rhs[q] < 0) return fail(SCOCG_EINVAL, "invalid problem " + std::to_string(q));
+        for (int64_t c = 0; c < n_rhs[q]; ++c) {
+            const int64_t j = rhs_idx[idx.size()];
+            if (j < 0 || j >= H[q]->d.n) return fail(SCOCG_EINVAL, "rhs_idx out of range in problem " + std::to_string(q));
+            idx.push_back(j);
+            rq.Hj.push_back(H[q]);
+        }
+    }
+    if (idx.empty()) return fail(SCOCG_EINVAL, "no right-hand sides");
+    if (o->keep_tape || o->refine) return fail(SCOCG_EINVAL, "batched solves keep no tape and do not refine");
+    rq.H = H[0];
+    rq.M = n_shift;
+    rq.K = (int64_t)idx.size();
+    rq.z = z;
+    rq.B = nullptr;
+    rq.unit_idx = idx.data();
+    rq.o = *o;
+    rq.o.check_true = 0;
+    rq.Xout = nullptr;
+    rq.projection = true;
+    rq.Gout = (double2 *)G;
+    rq.rep = rep;
+    return solve(rq, (hipStream_t)stream);
 }
 
 extern "C" int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double *z, const double *w, int64_t n_rhs,

@@ -119,9 +119,9 @@ __device__ inline bool seed_running(const SeedState &st, int TB)
     return st.status == SEED_RUNNING && st.step < TB;
 }
 
-__device__ inline double2 *ring_slot(const SolveDev &s, int slot, int64_t j)
+__device__ inline double2 *ring_slot(const SolveDev &s, int slot, const RhsDesc &d)
 {
-    return s.ring + ((int64_t)slot * s.K + j) * s.n;
+    return s.ring + (int64_t)slot * s.ntot + d.voff;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -134,13 +134,14 @@ __global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restri
     __shared__ double2 sh2[WG];
     __shared__ double sh1[WG];
     const int64_t j = blockIdx.y;
+    const RhsDesc d = s.desc[j];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     double2 b = cmk(0, 0);
-    if (row < s.n) {
-        if (B) b = B[j * s.n + row];
+    if (row < d.n) {
+        if (B) b = B[d.voff + row];
         else b = cmk(row == unit_idx[j] ? 1.0 : 0.0, 0.0);
-        ring_slot(s, 0, j)[row] = b;
-        s.p[j * s.n + row] = cmk(0, 0);
+        ring_slot(s, 0, d)[row] = b;
+        s.p[d.voff + row] = cmk(0, 0);
     }
     double2 bb = block_sum2(cmul(b, b), sh2);
     double nn = block_sum1(cabs2(b), sh1);
@@ -148,9 +149,9 @@ __global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restri
         s.part2[j * s.nblk + blockIdx.x] = bb;
         s.part1[j * s.nblk + blockIdx.x] = nn;
     }
-    if (!arrive_last(s.cnt, j, (uint32_t)s.nblk)) return;
-    double2 rho = sum_partials2(s.part2 + j * s.nblk, s.nblk, sh2);
-    double nb = sqrt(sum_partials1(s.part1 + j * s.nblk, s.nblk, sh1));
+    if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
+    double2 rho = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
+    double nb = sqrt(sum_partials1(s.part1 + j * s.nblk, gridDim.x, sh1));
     if (threadIdx.x == 0) {
         SeedState st;
         int sd = seed_idx[j];
@@ -204,11 +205,12 @@ __global__ void __launch_bounds__(WG) k_p_update(SolveDev s)
     const int64_t j = blockIdx.y;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
+    const RhsDesc d = s.desc[j];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (row >= s.n) return;
+    if (row >= d.n) return;
     const int slot = (st.base + st.step) % (s.TB + 1);
-    const double2 r = ring_slot(s, slot, j)[row];
-    double2 *pp = s.p + j * s.n + row;
+    const double2 r = ring_slot(s, slot, d)[row];
+    double2 *pp = s.p + d.voff + row;
     const double2 p = *pp;
     const double2 b = st.beta_prev;
     *pp = cfma(b, p, r);
@@ -218,35 +220,33 @@ __global__ void __launch_bounds__(WG) k_p_update(SolveDev s)
 // seed iteration, step 2: q = (z_s 1 - H) p, p.q, alpha_n = rho_n / (p.q)
 // One wave per 64-row slice, four slices per workgroup.
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_spmv(SolveDev s, const int64_t *__restrict__ slice_ptr,
-                                             const int32_t *__restrict__ slice_w,
-                                             const int32_t *__restrict__ ell_col,
-                                             const double *__restrict__ ell_val, int64_t nslices)
+__global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
 {
     __shared__ double2 sh2[WG];
     const int64_t j = blockIdx.y;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
+    const RhsDesc d = s.desc[j];
     const int lane = threadIdx.x & 63;
     const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t row = slice * 64 + lane;
-    const double2 *pj = s.p + j * s.n;
+    const double2 *pj = s.p + d.voff;
     double2 pq = cmk(0, 0);
-    if (slice < nslices) {
-        const int64_t off = slice_ptr[slice];
-        const int w = slice_w[slice];
+    if (slice < d.nslices) {
+        const int64_t off = d.slice_ptr[slice];
+        const int w = d.slice_w[slice];
         double ax = 0, ay = 0;
         for (int k = 0; k < w; ++k) {
-            const int c = ell_col[off + (int64_t)k * 64 + lane];
-            const double v = ell_val[off + (int64_t)k * 64 + lane];
+            const int c = d.ell_col[off + (int64_t)k * 64 + lane];
+            const double v = d.ell_val[off + (int64_t)k * 64 + lane];
             const double2 pc = pj[c];
             ax = fma(v, pc.x, ax);
             ay = fma(v, pc.y, ay);
         }
-        if (row < s.n) {
+        if (row < d.n) {
             const double2 pr = pj[row];
             const double2 qv = cfma(st.zs, pr, make_double2(-ax, -ay));
-            s.q[j * s.n + row] = qv;
+            s.q[d.voff + row] = qv;
             pq = cmul(pr, qv);
         }
     }
@@ -274,17 +274,18 @@ __global__ void __launch_bounds__(WG) k_r_update(SolveDev s)
     const int64_t j = blockIdx.y;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
+    const RhsDesc d = s.desc[j];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     const int slot = (st.base + st.step) % (s.TB + 1);
     const int nslot = (slot + 1) % (s.TB + 1);
     const double2 a = s.ahist[j * s.TB + st.step];
     double2 rr = cmk(0, 0);
     double nn = 0;
-    if (row < s.n) {
-        const double2 r = ring_slot(s, slot, j)[row];
-        const double2 q = s.q[j * s.n + row];
+    if (row < d.n) {
+        const double2 r = ring_slot(s, slot, d)[row];
+        const double2 q = s.q[d.voff + row];
         const double2 rn = cfma(make_double2(-a.x, -a.y), q, r);
-        ring_slot(s, nslot, j)[row] = rn;
+        ring_slot(s, nslot, d)[row] = rn;
         rr = cmul(rn, rn);
         nn = cabs2(rn);
     }
@@ -340,7 +341,7 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
         s.nact[pair] = 0;
         return;
     }
-    const double2 sig = csub(s.z[k], st.zs);
+    const double2 sig = csub(s.z[s.zper ? j : k], st.zs);
     double2 ap = st.a0, bp = st.b0;
     double2 pi = s.pi[pair], pip = s.pi_prev[pair], bk = s.beta_k[pair];
     double res = s.res[pair];
@@ -388,7 +389,7 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
         const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;
         const unsigned long long nv = s.X ? 2ull : 1ull;
         const unsigned long long rw = (st.iter - ns == 0) ? 1ull : 2ull;
-        atomicAdd(&s.stats[0], nv * rw * esz * (unsigned long long)s.n);
+        atomicAdd(&s.stats[0], nv * rw * esz * (unsigned long long)s.desc[j].n);
         atomicAdd(&s.stats[1], 1ull);
     }
 }
@@ -430,8 +431,9 @@ template <int TB, typename V, int NP, bool PROJ>
 __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed, const double2 *__restrict__ ring,
                                               const V *__restrict__ coef, const int32_t *__restrict__ nact,
                                               V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
-                                              const int64_t *__restrict__ proj_row, int64_t n, int64_t K, int64_t M,
-                                              int G, int ngroups)
+                                              const int64_t *__restrict__ proj_row,
+                                              const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
+                                              int ngroups)
 {
     const int64_t j = blockIdx.y / ngroups;
     const int g = blockIdx.y % ngroups;
@@ -439,14 +441,18 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     if (ns == 0) return;
     const int base = seed[j].base;
     const bool fresh = seed[j].iter == ns;
+    const int64_t n = desc[j].n;
+    const int64_t voff = desc[j].voff;
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (row >= n) return;
     V r[TB];
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
-        if (t < ns) r[t] = to_v<V>(ring[((int64_t)((base + t) % (TB + 1)) * K + j) * n + row]);
+        if (t < ns) r[t] = to_v<V>(ring[(int64_t)((base + t) % (TB + 1)) * ntot + voff + row]);
         else r[t] = to_v<V>(cmk(0, 0));
     }
+    X += M * voff;
+    P += M * voff;
     const int64_t k0 = (int64_t)g * G;
     const int64_t k1 = min(k0 + G, M);
     const int64_t prow = PROJ ? proj_row[j] : -1;
@@ -460,11 +466,11 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
             x[q] = to_v<V>(cmk(0, 0));
             u[q] = x[q];
             if (na[q] > 0 && !fresh) {
-                u[q] = ld_nt(P + pair * n + row);
+                u[q] = ld_nt(P + (k + q) * n + row);
                 if (PROJ) {
                     if (row == prow) x[q] = to_v<V>(Xproj[pair]);
                 } else {
-                    x[q] = ld_nt(X + pair * n + row);
+                    x[q] = ld_nt(X + (k + q) * n + row);
                 }
             }
         }
@@ -483,11 +489,11 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
         for (int q = 0; q < NP; ++q) {
             const int64_t pair = j * M + k + q;
             if (na[q] > 0) {
-                st_nt(P + pair * n + row, u[q]);
+                st_nt(P + (k + q) * n + row, u[q]);
                 if (PROJ) {
                     if (row == prow) Xproj[pair] = make_double2((double)x[q].x, (double)x[q].y);
                 } else {
-                    st_nt(X + pair * n + row, x[q]);
+                    st_nt(X + (k + q) * n + row, x[q]);
                 }
             }
         }
@@ -560,7 +566,8 @@ __global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
             w.status = SEED_STOPPED;
         }
         // the deferred update read the block's residual history once per row
-        if (st.step > 0) atomicAdd(&s.stats[0], (unsigned long long)st.step * 16ull * (unsigned long long)s.n);
+        if (st.step > 0)
+            atomicAdd(&s.stats[0], (unsigned long long)st.step * 16ull * (unsigned long long)s.desc[j].n);
         w.base = (st.base + st.step) % (s.TB + 1);
         w.step = 0;
         w.n_active = n_active;
@@ -618,22 +625,22 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
     const int64_t j = blockIdx.y;
     const SeedState st = s.seed[j];
     if (st.sw_target < 0) return;
+    const RhsDesc d = s.desc[j];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     double2 rr = cmk(0, 0);
-    if (row < s.n) {
-        double2 *rp = ring_slot(s, st.base, j) + row;
+    if (row < d.n) {
+        double2 *rp = ring_slot(s, st.base, d) + row;
         const double2 r = cmul(*rp, st.inv_pt);
         *rp = r;
-        V *P = (V *)s.P;
+        V *P = (V *)s.P + s.M * d.voff;
         const V sc = to_v<V>(st.inv_ppt);
         const V zero = to_v<V>(cmk(0, 0));
         for (int64_t k = 0; k < s.M; ++k) {
-            const int64_t pair = j * s.M + k;
-            if (!s.active[pair]) continue;
-            V *up = P + pair * s.n + row;
+            if (!s.active[j * s.M + k]) continue;
+            V *up = P + k * d.n + row;
             const V u = cfma(sc, *up, zero);
             *up = u;
-            if (k == st.sw_target) s.p[j * s.n + row] = make_double2((double)u.x, (double)u.y);
+            if (k == st.sw_target) s.p[d.voff + row] = make_double2((double)u.x, (double)u.y);
         }
         rr = cmul(r, r);
     }
@@ -665,69 +672,88 @@ __global__ void k_upcast(const float2 *__restrict__ src, double2 *__restrict__ d
     for (size_t k = i; k < count; k += stride) dst[k] = make_double2((double)src[k].x, (double)src[k].y);
 }
 
-// ||b - (z_k - H) x_k||^2 partials: grid (row blocks, pairs)
-__global__ void __launch_bounds__(WG) k_true_res_part(int64_t n, int64_t M, const double2 *__restrict__ z,
-                                                      const int64_t *__restrict__ slice_ptr,
-                                                      const int32_t *__restrict__ slice_w,
-                                                      const int32_t *__restrict__ ell_col,
-                                                      const double *__restrict__ ell_val, int64_t nslices,
-                                                      const double2 *__restrict__ B,
+// Residual of pair p = (j, k): r = b_j - (z - H) x_p in FP64 (z = z_k, or z_j when each rhs has
+// its own shift).  Writes the partial sums of |r|^2 per row block and, if rout is given, the
+// residual vector itself (row c of rout, stride rstride, for the c-th listed pair).
+// grid: (row blocks of the largest matrix, pairs).
+__global__ void __launch_bounds__(WG) k_true_res_part(const RhsDesc *__restrict__ desc, int64_t M, int zper,
+                                                      const double2 *__restrict__ z, const double2 *__restrict__ B,
                                                       const int64_t *__restrict__ unit_idx,
-                                                      const double2 *__restrict__ X, double *__restrict__ part,
-                                                      int64_t nblk, int64_t pair0)
+                                                      const double2 *__restrict__ X,
+                                                      const int64_t *__restrict__ pair_list,
+                                                      double2 *__restrict__ rout, int64_t rstride,
+                                                      double *__restrict__ part, int64_t nblk, int64_t c0)
 {
     __shared__ double sh1[WG];
-    const int64_t pair = pair0 + blockIdx.y;
+    const int64_t c = c0 + blockIdx.y;
+    const int64_t pair = pair_list ? pair_list[c] : c;
     const int64_t j = pair / M, k = pair % M;
+    const RhsDesc d = desc[j];
+    const double2 zk = z[zper ? j : k];
     const int lane = threadIdx.x & 63;
     const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t row = slice * 64 + lane;
-    const double2 *x = X + pair * n;
+    const double2 *x = X + M * d.voff + k * d.n;
     double e = 0;
-    if (slice < nslices) {
-        const int64_t off = slice_ptr[slice];
-        const int w = slice_w[slice];
+    if (slice < d.nslices) {
+        const int64_t off = d.slice_ptr[slice];
+        const int w = d.slice_w[slice];
         double ax = 0, ay = 0;
-        for (int c = 0; c < w; ++c) {
-            const int col = ell_col[off + (int64_t)c * 64 + lane];
-            const double v = ell_val[off + (int64_t)c * 64 + lane];
+        for (int q = 0; q < w; ++q) {
+            const int col = d.ell_col[off + (int64_t)q * 64 + lane];
+            const double v = d.ell_val[off + (int64_t)q * 64 + lane];
             const double2 xc = x[col];
-            ax += v * xc.x;
-            ay += v * xc.y;
+            ax = fma(v, xc.x, ax);
+            ay = fma(v, xc.y, ay);
         }
-        if (row < n) {
-            const double2 zx = cmul(z[k], x[row]);
+        if (row < d.n) {
             double2 b;
-            if (B) b = B[j * n + row];
+            if (B) b = B[d.voff + row];
             else b = cmk(row == unit_idx[j] ? 1.0 : 0.0, 0.0);
-            const double dx = b.x - (zx.x - ax), dy = b.y - (zx.y - ay);
-            e = dx * dx + dy * dy;
+            // b - (z x - H x)
+            const double2 zx = cfma(zk, x[row], make_double2(-ax, -ay));
+            const double2 r = csub(b, zx);
+            if (rout) rout[c * rstride + row] = r;
+            e = cabs2(r);
         }
     }
     e = block_sum1(e, sh1);
-    if (threadIdx.x == 0) part[pair * nblk + blockIdx.x] = e;
+    if (threadIdx.x == 0) part[c * nblk + blockIdx.x] = e;
 }
 
-__global__ void k_true_res_final(int64_t KM, int64_t M, const double *__restrict__ part, int64_t nblk,
-                                 const SeedState *__restrict__ seed, double *__restrict__ out)
+// x_p <- x_p + d_c for the listed pairs (refinement of a single-matrix solve, rows n)
+__global__ void k_add_correction(int64_t n, const int64_t *__restrict__ pair_list, const double2 *__restrict__ D,
+                                 double2 *__restrict__ X)
 {
-    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (pair >= KM) return;
-    double acc = 0;
-    for (int64_t b = 0; b < nblk; ++b) acc += part[pair * nblk + b];
-    const double nb = seed[pair / M].nb;
-    out[pair] = nb > 0 ? sqrt(acc) / nb : sqrt(acc);
+    const int64_t c = blockIdx.y;
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (row >= n) return;
+    const int64_t pair = pair_list[c];
+    X[pair * n + row] = cadd(X[pair * n + row], D[c * n + row]);
 }
 
-// G[k][c] = x_{c,k}[rows[c]] from full storage (X [K][M][n]) or the projected values
-__global__ void k_gather_diag(int64_t K, int64_t M, int64_t n, const double2 *__restrict__ X,
-                              const double2 *__restrict__ Xproj, const int64_t *__restrict__ rows,
-                              double2 *__restrict__ G)
+__global__ void k_true_res_final(int64_t count, int64_t M, const int64_t *__restrict__ pair_list,
+                                 const double *__restrict__ part, int64_t nblk, const double *__restrict__ bnorm,
+                                 double *__restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (c >= count) return;
+    double acc = 0;
+    for (int64_t b = 0; b < nblk; ++b) acc += part[c * nblk + b];
+    const int64_t pair = pair_list ? pair_list[c] : c;
+    const double nb = bnorm[pair / M];
+    out[c] = nb > 0 ? sqrt(acc) / nb : sqrt(acc);
+}
+
+// G[k][c] = x_{c,k}[rows[c]] from full storage or from the projected values
+__global__ void k_gather_diag(const RhsDesc *__restrict__ desc, int64_t K, int64_t M,
+                              const double2 *__restrict__ X, const double2 *__restrict__ Xproj,
+                              const int64_t *__restrict__ rows, double2 *__restrict__ G)
 {
     const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (pair >= K * M) return;
     const int64_t j = pair / M, k = pair % M;
-    G[k * K + j] = Xproj ? Xproj[pair] : X[pair * n + rows[j]];
+    G[k * K + j] = Xproj ? Xproj[pair] : X[M * desc[j].voff + k * desc[j].n + rows[j]];
 }
 
 // Density matrix, band energy and energy gradient of one batch of columns.
@@ -829,10 +855,9 @@ __global__ void k_pair_weights_conj(int64_t K, int64_t M, const double2 *__restr
 // ---------------------------------------------------------------------------------------
 static inline dim3 grid2(int64_t x, int64_t y) { return dim3((unsigned)x, (unsigned)y, 1); }
 
-hipError_t launch_init(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
+hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_idx,
                        const int32_t *seed_idx, int32_t limit, hipStream_t st)
 {
-    (void)H;
     hipLaunchKernelGGL(k_init, grid2(s.nblk, s.K), dim3(WG), 0, st, s, B, unit_idx, seed_idx, limit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -847,11 +872,9 @@ hipError_t launch_p_update(const SolveDev &s, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_spmv(const SolveDev &s, const DevCSR &H, hipStream_t st)
+hipError_t launch_spmv(const SolveDev &s, hipStream_t st)
 {
-    const int64_t gx = (H.nslices + 3) / 4;
-    hipLaunchKernelGGL(k_spmv, grid2(gx, s.K), dim3(WG), 0, st, s, H.d_slice_ptr, H.d_slice_w, H.d_ell_col,
-                       H.d_ell_val, H.nslices);
+    hipLaunchKernelGGL(k_spmv, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
     return hipGetLastError();
 }
 
@@ -879,10 +902,10 @@ static hipError_t flush_v(const SolveDev &s, hipStream_t st)
     const V *coef = (const V *)s.coef;
     if (s.Xproj)
         hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)nullptr,
-                           (V *)s.P, s.Xproj, s.proj_row, s.n, s.K, s.M, G, ng);
+                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng);
     else
         hipLaunchKernelGGL((k_flush<TB, V, NP, false>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)s.X,
-                           (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.n, s.K, s.M, G, ng);
+                           (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng);
     return hipGetLastError();
 }
 
@@ -932,35 +955,49 @@ hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t st)
 hipError_t launch_store_solution(const SolveDev &s, double2 *Xout, hipStream_t st)
 {
     if (s.precision == 0) return hipSuccess;
-    const size_t count = (size_t)(s.K * s.M * s.n);
+    const size_t count = (size_t)(s.M * s.ntot);
     size_t blocks = (count + WG - 1) / WG;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_upcast, dim3((unsigned)blocks), dim3(WG), 0, st, (const float2 *)s.X, Xout, count);
     return hipGetLastError();
 }
 
-hipError_t launch_true_residual(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
-                                const double2 *X64, double *part, double *out_res, hipStream_t st)
+hipError_t launch_residual(const SolveDev &s, const double2 *B, const int64_t *unit_idx, const double2 *X64,
+                           const int64_t *pair_list, int64_t count, const double *bnorm, double2 *rout,
+                           double *part, double *out_res, hipStream_t st)
 {
-    const int64_t gx = (H.nslices + 3) / 4;
-    const int64_t KM = s.K * s.M;
+    const int64_t gx = s.nblk;
     const int64_t chunk = 32768;
-    for (int64_t p0 = 0; p0 < KM; p0 += chunk) {
-        const int64_t np = (KM - p0) < chunk ? (KM - p0) : chunk;
-        hipLaunchKernelGGL(k_true_res_part, grid2(gx, np), dim3(WG), 0, st, s.n, s.M, s.z, H.d_slice_ptr,
-                           H.d_slice_w, H.d_ell_col, H.d_ell_val, H.nslices, B, unit_idx, X64, part, gx, p0);
+    for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+        const int64_t nc = (count - c0) < chunk ? (count - c0) : chunk;
+        hipLaunchKernelGGL(k_true_res_part, grid2(gx, nc), dim3(WG), 0, st, s.desc, s.M, s.zper, s.z, B, unit_idx,
+                           X64, pair_list, rout, s.n, part, gx, c0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_true_res_final, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, KM, s.M, part, gx,
-                       s.seed, out_res);
+    hipLaunchKernelGGL(k_true_res_final, dim3((unsigned)((count + WG - 1) / WG)), dim3(WG), 0, st, count, s.M, pair_list,
+                       part, gx, bnorm, out_res);
     return hipGetLastError();
+}
+
+hipError_t launch_add_correction(int64_t n, const int64_t *pair_list, int64_t count, const double2 *D, double2 *X,
+                                 hipStream_t st)
+{
+    const int64_t chunk = 32768;
+    for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+        const int64_t nc = (count - c0) < chunk ? (count - c0) : chunk;
+        hipLaunchKernelGGL(k_add_correction, grid2((n + WG - 1) / WG, nc), dim3(WG), 0, st, n, pair_list + c0,
+                           D + c0 * n, X);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_gather_diag(const SolveDev &s, const int64_t *rows, double2 *G, hipStream_t st)
 {
     const int64_t KM = s.K * s.M;
-    hipLaunchKernelGGL(k_gather_diag, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, s.K, s.M, s.n,
+    hipLaunchKernelGGL(k_gather_diag, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, s.desc, s.K, s.M,
                        (const double2 *)s.X, s.Xproj, rows, G);
     return hipGetLastError();
 }

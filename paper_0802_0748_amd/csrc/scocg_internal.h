@@ -85,9 +85,26 @@ struct DevCSR {
     int max_w;            // widest slice
 };
 
+// ---- per right-hand side: its matrix and where its vectors live ----
+// A solve may mix Hamiltonians of different sizes (one per right-hand side or shared).
+// Vectors of rhs j occupy [voff, voff + n) of every [sum n]-long array (r ring slot, p,
+// q, B); its pair vectors (x_k, u_k) start at M * voff + k * n.
+struct RhsDesc {
+    const int64_t *slice_ptr;
+    const int32_t *slice_w;
+    const int32_t *ell_col;
+    const double *ell_val;
+    int64_t nslices;
+    int64_t n;
+    int64_t voff;
+    int64_t pad;
+};
+
 // ---- launch wrappers (kernels.hip) ----
 struct SolveDev {
-    int64_t n, K, M;
+    const RhsDesc *desc;       // [K]
+    int64_t ntot;              // sum of n over right-hand sides (stride of one ring slot)
+    int64_t n, K, M;           // n: the largest row count
     int TB;                    // block length (ring has TB+1 slots)
     int precision;             // 0 FP64 storage, 1 FP32
     int fixed;                 // fixed-iteration mode
@@ -112,13 +129,14 @@ struct SolveDev {
     uint32_t *cnt;             // [K] last-block counters
     int64_t nblk;              // row blocks of 256
     int shifts_per_wg;
+    int zper;                  // 1: one shift per rhs (M = 1, z has K entries), used by refinement
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
 };
 
-hipError_t launch_init(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
+hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_idx,
                        const int32_t *seed_idx, int32_t limit, hipStream_t st);
 hipError_t launch_p_update(const SolveDev &s, hipStream_t st);
-hipError_t launch_spmv(const SolveDev &s, const DevCSR &H, hipStream_t st);
+hipError_t launch_spmv(const SolveDev &s, hipStream_t st);
 hipError_t launch_r_update(const SolveDev &s, hipStream_t st);
 hipError_t launch_pair_scalars(const SolveDev &s, hipStream_t st);
 hipError_t launch_flush(const SolveDev &s, hipStream_t st);
@@ -126,8 +144,14 @@ hipError_t launch_block_finalize(const SolveDev &s, hipStream_t st);
 hipError_t launch_switch_vectors(const SolveDev &s, hipStream_t st);
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t st);
 hipError_t launch_store_solution(const SolveDev &s, double2 *Xout, hipStream_t st);
-hipError_t launch_true_residual(const SolveDev &s, const DevCSR &H, const double2 *B, const int64_t *unit_idx,
-                                const double2 *X64, double *part, double *out_res, hipStream_t st);
+// r = b - (z - H) x for `count` pairs (pair_list[c], or c if pair_list is null): relative norms
+// into out_res[c] (divided by bnorm[rhs]) and, if rout is given, the vectors into rout[c][n].
+// part needs count * ceil(n / 256) doubles.
+hipError_t launch_residual(const SolveDev &s, const double2 *B, const int64_t *unit_idx, const double2 *X64,
+                           const int64_t *pair_list, int64_t count, const double *bnorm, double2 *rout,
+                           double *part, double *out_res, hipStream_t st);
+hipError_t launch_add_correction(int64_t n, const int64_t *pair_list, int64_t count, const double2 *D, double2 *X,
+                                 hipStream_t st);
 hipError_t launch_gather_diag(const SolveDev &s, const int64_t *rows, double2 *G, hipStream_t st);
 hipError_t launch_density_rho(int64_t n, int64_t K, int64_t M, const double2 *X, const int64_t *cols_of_rhs,
                               const int64_t *row_ptr, const int32_t *col, const double2 *w, const double2 *z,

@@ -1,0 +1,83 @@
+"""Full-size workloads on the GPU, in the launch configuration the benchmark times.
+
+The oracle cannot run these end to end in seconds, so they are checked on sampled
+pairs (plain per-shift COCG from the oracle) and through properties that hold at any
+size: every pair's FP64 true residual (computed on the GPU and, for samples, on the
+CPU) is at the tolerance, and two converged answers are within the residual bound.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import config2_diamond, config3_hubbard
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _S():
+    import paper_0802_0748_amd as S
+
+    return S
+
+
+def _cpu_true_residual(H, z, x, b):
+    A = H.to_scipy()
+    r = b - (z * x - A @ x)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+def test_diamond_bench_configuration():
+    """Diamond 8x8x8 (16384 rows), 256 shifts x 256 unit RHS, FP64, tol 1e-8: every pair
+    converges; true residuals at the tolerance; sampled pairs agree with plain COCG."""
+    S = _S()
+    p = config2_diamond()
+    H = S.Hamiltonian.from_csr(p.H)
+    K, M, n = p.n_rhs, len(p.z), p.H.n
+    B = torch.zeros((K, n), dtype=torch.complex128, device="cuda")
+    B[torch.arange(K), torch.from_numpy(p.rhs_idx).cuda()] = 1.0
+    t0 = time.perf_counter()
+    X, rep, _, rc = S.shifted_cocg_solve(H, p.z, B, tol=1e-8, max_iter=40000, check_true=True)
+    torch.cuda.synchronize()
+    print(f"diamond full solve {time.perf_counter() - t0:.1f} s, switches {S.last_timing()['switches']}, "
+          f"max true residual {rep['res_true'].max():.2e}", flush=True)
+    assert rc == 0
+    assert np.all(rep["status"] == 0)
+    assert rep["res_true"].max() < 20 * 1e-8
+    rng = np.random.default_rng(0)
+    for j, k in [(0, 128), (int(rng.integers(K)), int(rng.integers(M)))]:
+        x_gpu = X[j, k].cpu().numpy()
+        b = O.unit(n, int(p.rhs_idx[j]))
+        assert _cpu_true_residual(p.H, p.z[k], x_gpu, b) < 20 * 1e-8
+        ref = O.cocg(p.H, p.z[k], b, tol=1e-8, max_iter=60000)
+        assert ref["status"] == 0
+        r_orc = O.true_residual(p.H, p.z[k], ref["x"], b)
+        bound = (rep["res_true"][j, k] + r_orc) / p.z[k].imag
+        assert np.linalg.norm(x_gpu - ref["x"]) <= bound * (1 + 1e-6)
+
+
+def test_hubbard_full_size():
+    """Extended Hubbard ring, 11,778,624 rows, 189,364,032 entries, 128 shifts, one complex
+    RHS, FP64: all pairs converge, true residuals at the tolerance (GPU for all pairs, CPU
+    for samples)."""
+    S = _S()
+    t0 = time.perf_counter()
+    p = config3_hubbard()
+    H = S.Hamiltonian.from_csr(p.H, validate=True)
+    print(f"hubbard build+upload {time.perf_counter() - t0:.1f} s", flush=True)
+    B = torch.from_numpy(p.B).cuda()
+    t0 = time.perf_counter()
+    X, rep, _, rc = S.shifted_cocg_solve(H, p.z, B, tol=1e-8, max_iter=20000, check_true=True)
+    torch.cuda.synchronize()
+    t = S.last_timing()
+    print(f"hubbard solve {time.perf_counter() - t0:.1f} s, iterations {t['iterations']}, switches "
+          f"{t['switches']}, max true residual {rep['res_true'].max():.2e}, max iters {rep['iters'].max()}",
+          flush=True)
+    assert rc == 0
+    assert rep["res_true"].max() < 20 * 1e-8
+    for k in (0, 64, 127):
+        x = X[0, k].cpu().numpy()
+        assert _cpu_true_residual(p.H, p.z[k], x, p.B[0]) < 20 * 1e-8

@@ -213,6 +213,57 @@ def test_fp32_storage_matches_oracle_to_1e5():
     assert max(errs) < 1e-5
 
 
+def test_fp32_storage_with_fp64_refinement_reaches_tolerance():
+    """FP32 storage alone leaves true residuals near 1e-5; the FP64 per-pair refinement brings
+    every pair below the tolerance and into the oracle's residual bound."""
+    S = _S()
+    rng = np.random.default_rng(6)
+    L = 7
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    z = np.linspace(-6, 6, 12) + 0.05j
+    B = np.zeros((2, Hc.n), dtype=complex)
+    B[0, 3] = 1
+    B[1] = rng.normal(size=Hc.n) + 1j * rng.normal(size=Hc.n)
+    H = S.Hamiltonian.from_csr(Hc)
+    tol = 1e-9
+    X0, rep0, _, _ = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=tol, max_iter=5000,
+                                          precision="fp32", check_true=True)
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=tol, max_iter=5000,
+                                         precision="fp32", refine=3)
+    print("fp32 true residual before/after refinement:", rep0["res_true"].max(), rep["res_true"].max())
+    assert rep0["res_true"].max() > tol
+    assert rep["res_true"].max() <= tol
+    Xg = X.cpu().numpy()
+    for j in range(2):
+        ref = O.shifted_cocg(Hc, z, B[j], tol=tol, max_iter=5000)
+        for k in range(len(z)):
+            d, bound = _bound_check(Hc, z[k], B[j], Xg[j, k], rep["res_true"][j, k], ref["X"][k])
+            assert d <= bound * (1 + 1e-6), (j, k, d, bound)
+
+
+def test_batched_uneven_hamiltonians_equal_separate_solves():
+    """Several lattices of different sizes in one solve: each right-hand side gives the same
+    bits as its own single-matrix solve (zero partial sums of idle row blocks add exactly),
+    and matches the oracle."""
+    S = _S()
+    rng = np.random.default_rng(9)
+    Ls = [5, 9, 6, 8]
+    Hcs = [simple_cubic(L, rng.uniform(-2, 2, L ** 3)) for L in Ls]
+    Hs = [S.Hamiltonian.from_csr(h) for h in Hcs]
+    rhs = [np.sort(rng.choice(h.n, size=3, replace=False)) for h in Hcs]
+    z = np.linspace(-6, 6, 10) + 0.1j
+    Gs, reps, rc = S.greens_diag_batched(Hs, z, rhs, tol=1e-10, max_iter=4000)
+    assert rc == 0
+    for q in range(len(Ls)):
+        G1, rep1, _, _ = S.greens_diag(Hs[q], z, rhs[q], tol=1e-10, max_iter=4000)
+        assert np.array_equal(Gs[q].cpu().numpy(), G1.cpu().numpy())
+        assert np.array_equal(reps[q]["iters"], rep1["iters"])
+        for c, j in enumerate(rhs[q]):
+            ref = O.shifted_cocg(Hcs[q], z, O.unit(Hcs[q].n, int(j)), tol=1e-10, max_iter=4000)
+            g = Gs[q].cpu().numpy()[:, c]
+            assert np.max(np.abs(g - ref["X"][:, j]) * z.imag) < 2 * 20 * 1e-10
+
+
 def test_zero_rhs_and_breakdown():
     S = _S()
     rng = np.random.default_rng(0)
