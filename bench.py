@@ -140,7 +140,7 @@ def main():
         "config": {"workload": f"diamond 8x8x8 cells, 4 orbitals/atom (n={n}, nnz={p.H.nnz}), {M} shifts "
                                f"eta=0.005, {K} unit RHS, tol {args.tol:g}, max_iter {args.max_iter}",
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
-                   "block": args.block or 8},
+                   "block": args.block or 16},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_flush (deferred per-shift update)",

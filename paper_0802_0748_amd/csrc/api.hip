@@ -342,7 +342,9 @@ int solve(SolveRequest &rq, hipStream_t st)
     for (int64_t k = 0; k < nz; ++k)
         if (!std::isfinite(rq.z[2 * k]) || !std::isfinite(rq.z[2 * k + 1]))
             return fail(SCOCG_EINVAL, "non-finite shift");
-    int TB = o.block > 0 ? o.block : 8;
+    // 16 iterations per deferred update: the update streams x_k, u_k at copy bandwidth and
+    // its arithmetic (8 fused multiply-adds per step) still hides under the memory time
+    int TB = o.block > 0 ? o.block : 16;
     if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16)
         return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8 or 16");
     int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 32);
@@ -407,7 +409,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     ALLOC(bz, nz * sizeof(double2));
     ALLOC(bseed, K * sizeof(SeedState));
     ALLOC(bring, (size_t)(TB + 1) * vec * sizeof(double2));
-    ALLOC(bp, vec * sizeof(double2));
+    ALLOC(bp, 2 * vec * sizeof(double2));
     ALLOC(bq, vec * sizeof(double2));
     ALLOC(bP, (size_t)M * ntot * esz);
     const bool x_is_out = need_full && o.precision == 0 && rq.Xout && !rq.keepX;
@@ -504,11 +506,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     if (use_graph) {
         HIPCHK(hipStreamCreateWithFlags(&gr.cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
-        for (int t = 0; t < TB; ++t) {
-            HIPCHK(launch_p_update(s, gr.cap));
-            HIPCHK(launch_spmv(s,gr.cap));
-            HIPCHK(launch_r_update(s, gr.cap));
-        }
+        for (int t = 0; t < TB; ++t) HIPCHK(launch_seed_iteration(s, gr.cap));
         HIPCHK(launch_pair_scalars(s, gr.cap));
         HIPCHK(hipStreamEndCapture(gr.cap, &gr.ga));
         HIPCHK(hipGraphInstantiate(&gr.ea, gr.ga, nullptr, nullptr, 0));
@@ -530,11 +528,7 @@ int solve(SolveRequest &rq, hipStream_t st)
             if (use_graph) {
                 HIPCHK(hipGraphLaunch(gr.ea, st));
             } else {
-                for (int t = 0; t < TB; ++t) {
-                    HIPCHK(launch_p_update(s, st));
-                    HIPCHK(launch_spmv(s,st));
-                    HIPCHK(launch_r_update(s, st));
-                }
+                for (int t = 0; t < TB; ++t) HIPCHK(launch_seed_iteration(s, st));
                 HIPCHK(launch_pair_scalars(s, st));
             }
             if (g_profiling) HIPCHK(hipEventRecord(fev[2 * b], st));

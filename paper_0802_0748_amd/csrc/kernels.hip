@@ -124,6 +124,12 @@ __device__ inline double2 *ring_slot(const SolveDev &s, int slot, const RhsDesc 
     return s.ring + (int64_t)slot * s.ntot + d.voff;
 }
 
+// seed direction buffer of a parity (p_n lives in buffer n mod 2)
+__device__ inline double2 *p_buf(const SolveDev &s, const RhsDesc &d, int parity)
+{
+    return s.p + (int64_t)parity * s.ntot + d.voff;
+}
+
 // ---------------------------------------------------------------------------------------
 // initialisation: r_0 = b, p = 0, rho = b.b, ||b||, seed state
 // ---------------------------------------------------------------------------------------
@@ -141,7 +147,8 @@ __global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restri
         if (B) b = B[d.voff + row];
         else b = cmk(row == unit_idx[j] ? 1.0 : 0.0, 0.0);
         ring_slot(s, 0, d)[row] = b;
-        s.p[d.voff + row] = cmk(0, 0);
+        p_buf(s, d, 0)[row] = cmk(0, 0);
+        p_buf(s, d, 1)[row] = cmk(0, 0);
     }
     double2 bb = block_sum2(cmul(b, b), sh2);
     double nn = block_sum1(cabs2(b), sh1);
@@ -198,29 +205,16 @@ __global__ void __launch_bounds__(WG) k_init_pairs(SolveDev s)
 }
 
 // ---------------------------------------------------------------------------------------
-// seed iteration, step 1: p_n = r_n + beta_{n-1} p_{n-1}
+// One seed iteration is four launches, none of which needs a grid-wide fence (kernel
+// boundaries order them):
+//   k_pspmv   p_n = r_n + beta_{n-1} p_{n-1};  q = (z_s 1 - H) p_n;  partial sums of p_n.q
+//   k_alpha   alpha_n = rho_n / (p_n.q)                        (one workgroup per rhs)
+//   k_rupd    r_{n+1} = r_n - alpha_n q;  partial sums of r.r and |r|^2
+//   k_beta    rho_{n+1}, ||r_{n+1}||, beta_n, convergence of the seed (one workgroup per rhs)
+// p is double-buffered by iteration parity: the SpMV needs p_n at neighbouring rows, which
+// it forms on the fly from r_n and p_{n-1} (same fused multiply-add as for its own rows).
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_p_update(SolveDev s)
-{
-    const int64_t j = blockIdx.y;
-    const SeedState st = s.seed[j];
-    if (!seed_running(st, s.TB)) return;
-    const RhsDesc d = s.desc[j];
-    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (row >= d.n) return;
-    const int slot = (st.base + st.step) % (s.TB + 1);
-    const double2 r = ring_slot(s, slot, d)[row];
-    double2 *pp = s.p + d.voff + row;
-    const double2 p = *pp;
-    const double2 b = st.beta_prev;
-    *pp = cfma(b, p, r);
-}
-
-// ---------------------------------------------------------------------------------------
-// seed iteration, step 2: q = (z_s 1 - H) p, p.q, alpha_n = rho_n / (p.q)
-// One wave per 64-row slice, four slices per workgroup.
-// ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
+__global__ void __launch_bounds__(WG) k_pspmv(SolveDev s)
 {
     __shared__ double2 sh2[WG];
     const int64_t j = blockIdx.y;
@@ -230,7 +224,11 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
     const int lane = threadIdx.x & 63;
     const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t row = slice * 64 + lane;
-    const double2 *pj = s.p + d.voff;
+    const int par = st.iter & 1;
+    const double2 *pold = p_buf(s, d, par ^ 1);
+    double2 *pnew = p_buf(s, d, par);
+    const double2 *r = ring_slot(s, (st.base + st.step) % (s.TB + 1), d);
+    const double2 b = st.beta_prev;
     double2 pq = cmk(0, 0);
     if (slice < d.nslices) {
         const int64_t off = d.slice_ptr[slice];
@@ -239,12 +237,13 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
         for (int k = 0; k < w; ++k) {
             const int c = d.ell_col[off + (int64_t)k * 64 + lane];
             const double v = d.ell_val[off + (int64_t)k * 64 + lane];
-            const double2 pc = pj[c];
+            const double2 pc = cfma(b, pold[c], r[c]);
             ax = fma(v, pc.x, ax);
             ay = fma(v, pc.y, ay);
         }
         if (row < d.n) {
-            const double2 pr = pj[row];
+            const double2 pr = cfma(b, pold[row], r[row]);
+            pnew[row] = pr;
             const double2 qv = cfma(st.zs, pr, make_double2(-ax, -ay));
             s.q[d.voff + row] = qv;
             pq = cmul(pr, qv);
@@ -252,22 +251,22 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
     }
     pq = block_sum2(pq, sh2);
     if (threadIdx.x == 0) s.part2[j * s.nblk + blockIdx.x] = pq;
-    if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
-    const double2 tot = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
-    if (threadIdx.x == 0) {
-        if (cis0(tot) || cis0(st.rho)) {
-            s.seed[j].status = SEED_BREAKDOWN;
-        } else {
-            s.ahist[j * s.TB + st.step] = cdiv(st.rho, tot);
-        }
-    }
-    reset_counter(s.cnt, j);
 }
 
-// ---------------------------------------------------------------------------------------
-// seed iteration, step 3: r_{n+1} = r_n - alpha_n q, rho_{n+1}, ||r_{n+1}||, beta_n
-// ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_r_update(SolveDev s)
+__global__ void __launch_bounds__(WG) k_alpha(SolveDev s)
+{
+    __shared__ double2 sh2[WG];
+    const int64_t j = blockIdx.x;
+    const SeedState st = s.seed[j];
+    if (!seed_running(st, s.TB)) return;
+    const double2 tot = sum_partials2(s.part2 + j * s.nblk, s.nblk, sh2);
+    if (threadIdx.x == 0) {
+        if (cis0(tot) || cis0(st.rho)) s.seed[j].status = SEED_BREAKDOWN;
+        else s.ahist[j * s.TB + st.step] = cdiv(st.rho, tot);
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_rupd(SolveDev s)
 {
     __shared__ double2 sh2[WG];
     __shared__ double sh1[WG];
@@ -295,10 +294,19 @@ __global__ void __launch_bounds__(WG) k_r_update(SolveDev s)
         s.part2[j * s.nblk + blockIdx.x] = rr;
         s.part1[j * s.nblk + blockIdx.x] = nn;
     }
-    if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
-    const double2 rho_new = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
-    const double rnorm = sqrt(sum_partials1(s.part1 + j * s.nblk, gridDim.x, sh1));
+}
+
+__global__ void __launch_bounds__(WG) k_beta(SolveDev s)
+{
+    __shared__ double2 sh2[WG];
+    __shared__ double sh1[WG];
+    const int64_t j = blockIdx.x;
+    const SeedState st = s.seed[j];
+    if (!seed_running(st, s.TB)) return;
+    const double2 rho_new = sum_partials2(s.part2 + j * s.nblk, s.nblk, sh2);
+    const double rnorm = sqrt(sum_partials1(s.part1 + j * s.nblk, s.nblk, sh1));
     if (threadIdx.x == 0) {
+        const double2 a = s.ahist[j * s.TB + st.step];
         const double2 beta = cdiv(rho_new, st.rho);
         s.bhist[j * s.TB + st.step] = beta;
         s.rnhist[j * s.TB + st.step] = rnorm;
@@ -313,7 +321,6 @@ __global__ void __launch_bounds__(WG) k_r_update(SolveDev s)
         if (it >= st.limit) w->status = SEED_LIMIT;
         else if (!s.fixed && s.switching && rnorm / st.nb < s.tol) w->status = SEED_PAUSED;
     }
-    reset_counter(s.cnt, j);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -330,16 +337,14 @@ __global__ void __launch_bounds__(WG) k_r_update(SolveDev s)
 // writes (a'_n, b'_n) for every step of the block in which the pair is still active.
 // ---------------------------------------------------------------------------------------
 template <typename V>
-__global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
+__device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t pair)
 {
-    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (pair >= s.K * s.M) return;
     const int64_t j = pair / s.M, k = pair % s.M;
     const SeedState st = s.seed[j];
     const int ns = st.step;
     if (!s.active[pair] || ns == 0) {
         s.nact[pair] = 0;
-        return;
+        return 0ull;
     }
     const double2 sig = csub(s.z[s.zper ? j : k], st.zs);
     double2 ap = st.a0, bp = st.b0;
@@ -383,14 +388,35 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
     s.pstatus[pair] = status;
     s.active[pair] = act;
     s.nact[pair] = na;
-    if (na > 0) {
-        // algorithmic bytes of this pair's deferred update: u_k (and x_k unless projected)
-        // written once, and read once unless this is the first block
-        const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;
-        const unsigned long long nv = s.X ? 2ull : 1ull;
-        const unsigned long long rw = (st.iter - ns == 0) ? 1ull : 2ull;
-        atomicAdd(&s.stats[0], nv * rw * esz * (unsigned long long)s.desc[j].n);
-        atomicAdd(&s.stats[1], 1ull);
+    if (na == 0) return 0ull;
+    // algorithmic bytes of this pair's deferred update: u_k (and x_k unless projected)
+    // written once, and read once unless this is the first block
+    const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;
+    const unsigned long long nv = s.X ? 2ull : 1ull;
+    const unsigned long long rw = (st.iter - ns == 0) ? 1ull : 2ull;
+    return nv * rw * esz * (unsigned long long)s.desc[j].n;
+}
+
+template <typename V>
+__global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
+{
+    __shared__ unsigned long long shb[WG];
+    __shared__ unsigned int shc[WG];
+    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const unsigned long long b = pair < s.K * s.M ? pair_scalars_one<V>(s, pair) : 0ull;
+    shb[threadIdx.x] = b;
+    shc[threadIdx.x] = b > 0 ? 1u : 0u;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            shb[threadIdx.x] += shb[threadIdx.x + h];
+            shc[threadIdx.x] += shc[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && shc[0] > 0) {
+        atomicAdd(&s.stats[0], shb[0]);
+        atomicAdd(&s.stats[1], (unsigned long long)shc[0]);
     }
 }
 
@@ -640,7 +666,7 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
             V *up = P + k * d.n + row;
             const V u = cfma(sc, *up, zero);
             *up = u;
-            if (k == st.sw_target) s.p[d.voff + row] = make_double2((double)u.x, (double)u.y);
+            if (k == st.sw_target) p_buf(s, d, (st.iter + 1) & 1)[row] = make_double2((double)u.x, (double)u.y);
         }
         rr = cmul(r, r);
     }
@@ -866,21 +892,12 @@ hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_
     return hipGetLastError();
 }
 
-hipError_t launch_p_update(const SolveDev &s, hipStream_t st)
+hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_p_update, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_spmv(const SolveDev &s, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_spmv, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_r_update(const SolveDev &s, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_r_update, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    hipLaunchKernelGGL(k_pspmv, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    hipLaunchKernelGGL(k_alpha, dim3((unsigned)s.K), dim3(WG), 0, st, s);
+    hipLaunchKernelGGL(k_rupd, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    hipLaunchKernelGGL(k_beta, dim3((unsigned)s.K), dim3(WG), 0, st, s);
     return hipGetLastError();
 }
 

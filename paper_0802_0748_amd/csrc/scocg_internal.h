@@ -135,9 +135,8 @@ struct SolveDev {
 
 hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_idx,
                        const int32_t *seed_idx, int32_t limit, hipStream_t st);
-hipError_t launch_p_update(const SolveDev &s, hipStream_t st);
-hipError_t launch_spmv(const SolveDev &s, hipStream_t st);
-hipError_t launch_r_update(const SolveDev &s, hipStream_t st);
+// one seed iteration (four launches, see kernels.hip)
+hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st);
 hipError_t launch_pair_scalars(const SolveDev &s, hipStream_t st);
 hipError_t launch_flush(const SolveDev &s, hipStream_t st);
 hipError_t launch_block_finalize(const SolveDev &s, hipStream_t st);
