@@ -394,6 +394,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.nblk = (n + 255) / 256;
     s.shifts_per_wg = G;
     s.zper = rq.zper ? 1 : 0;
+    s.spmv_rb = (uniform && K >= 2) ? 2 : 1;
 
     DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
         brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc;

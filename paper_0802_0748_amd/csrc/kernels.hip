@@ -1,41 +1,18 @@
-// HIP kernels of the shifted-COCG solver (gfx950, wave64).
+// HIP kernels of the shifted-COCG solver (gfx950, wave64): seed iteration, shift scalars,
+// end-of-block decisions, residuals and observables.  The deferred per-shift update is in
+// flush.hip.
 //
-// Data layout in HBM (n rows, K right-hand sides, M shifts):
-//   seed vectors r (ring of TB+1 slots), p, q : [K][n] complex FP64, one contiguous vector per rhs
-//   per-shift vectors x_k, p_k               : [K][M][n] (pair-major), FP64 or FP32 complex
-//   H                                        : 64-row slices, each slice stored column-slot-major
-//                                              (slot k of the 64 rows is contiguous), FP64 values
-// All reductions are fixed-order: every workgroup writes a partial, the last workgroup to
-// arrive (counter per rhs) sums the partials in index order, so results do not depend on
-// scheduling and a rhs gives the same bits whether it is solved alone or in a batch.
-#include "scocg_internal.h"
-
-// No implicit contraction: every fused multiply-add below is written out, so the
-// arithmetic (and its rounding) is the same in every template instance.
-#pragma clang fp contract(off)
+// Data layout in HBM (n rows, K right-hand sides, M shifts; see RhsDesc for mixed sizes):
+//   seed vectors r (ring of TB+1 slots), p (two parities), q : one contiguous vector per rhs
+//   per-shift vectors x_k, u_k                                : pair-major, FP64 or FP32 complex
+//   H : 64-row slices, each slice stored column-slot-major (slot k of the 64 rows is
+//       contiguous), FP64 values
+// All reductions are fixed-order: every workgroup writes a partial and one workgroup sums
+// the partials in index order, so results do not depend on scheduling and a rhs gives the
+// same bits whether it is solved alone or in a batch.
+#include "device_common.h"
 
 namespace scocg {
-
-static constexpr int WG = 256;
-
-// a * b + c with explicit fused multiply-adds
-__device__ inline double2 cfma(double2 a, double2 b, double2 c)
-{
-    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
-}
-__device__ inline float2 cfma(float2 a, float2 b, float2 c)
-{
-    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
-}
-__device__ inline double rfma(double a, double b, double c) { return fma(a, b, c); }
-__device__ inline float rfma(float a, float b, float c) { return fmaf(a, b, c); }
-
-template <typename V>
-__device__ inline V to_v(double2 a);
-template <>
-__device__ inline double2 to_v<double2>(double2 a) { return a; }
-template <>
-__device__ inline float2 to_v<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
 
 // ---------------------------------------------------------------------------------------
 // reductions
@@ -124,7 +101,7 @@ __device__ inline double2 *ring_slot(const SolveDev &s, int slot, const RhsDesc 
     return s.ring + (int64_t)slot * s.ntot + d.voff;
 }
 
-// seed direction buffer of a parity (p_n lives in buffer n mod 2)
+// seed direction buffer (a second parity buffer is kept zeroed and unused)
 __device__ inline double2 *p_buf(const SolveDev &s, const RhsDesc &d, int parity)
 {
     return s.p + (int64_t)parity * s.ntot + d.voff;
@@ -205,52 +182,110 @@ __global__ void __launch_bounds__(WG) k_init_pairs(SolveDev s)
 }
 
 // ---------------------------------------------------------------------------------------
-// One seed iteration is four launches, none of which needs a grid-wide fence (kernel
+// One seed iteration is five launches, none of which needs a grid-wide fence (kernel
 // boundaries order them):
-//   k_pspmv   p_n = r_n + beta_{n-1} p_{n-1};  q = (z_s 1 - H) p_n;  partial sums of p_n.q
-//   k_alpha   alpha_n = rho_n / (p_n.q)                        (one workgroup per rhs)
+//   k_pupd    p_n = r_n + beta_{n-1} p_{n-1}                      (elementwise, in place)
+//   k_spmv    q = (z_s 1 - H) p_n;  partial sums of p_n.q         (RB right-hand sides per thread)
+//   k_alpha   alpha_n = rho_n / (p_n.q)                           (one workgroup per rhs)
 //   k_rupd    r_{n+1} = r_n - alpha_n q;  partial sums of r.r and |r|^2
 //   k_beta    rho_{n+1}, ||r_{n+1}||, beta_n, convergence of the seed (one workgroup per rhs)
-// p is double-buffered by iteration parity: the SpMV needs p_n at neighbouring rows, which
-// it forms on the fly from r_n and p_{n-1} (same fused multiply-add as for its own rows).
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_pspmv(SolveDev s)
+__global__ void __launch_bounds__(WG) k_pupd(SolveDev s)
 {
-    __shared__ double2 sh2[WG];
     const int64_t j = blockIdx.y;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
     const RhsDesc d = s.desc[j];
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (row >= d.n) return;
+    double2 *p = p_buf(s, d, 0) + row;
+    *p = cfma(st.beta_prev, *p, ring_slot(s, (st.base + st.step) % (s.TB + 1), d)[row]);
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by linear index.  With at least 8 groups of
+// right-hand sides every row block of one group is placed on the same XCD, so its vectors are
+// fetched into one L2 only: the 1-D grid has nblk * 8 * ceil(G / 8) workgroups and linear index
+// L runs group 8 * ((L / 8) / nblk) + L % 8, row block (L / 8) % nblk.  With fewer groups the
+// row blocks of each group are spread over all XCDs (group L / nblk, row block L % nblk).
+__device__ inline bool xcd_group_block(int64_t nblk, int64_t G, int64_t &g, int64_t &rb)
+{
+    const int64_t L = blockIdx.x;
+    if (G < 8) {
+        g = L / nblk;
+        rb = L % nblk;
+        return g < G;
+    }
+    const int64_t t = L >> 3;
+    g = 8 * (t / nblk) + (L & 7);
+    rb = t % nblk;
+    return g < G;
+}
+
+// q = (z_s 1 - H) p for RB right-hand sides that share one matrix (consecutive rhs j0 .. j0+RB-1):
+// the column and value of each slot are loaded once and serve all RB gathers.
+template <int RB>
+__global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
+{
+    __shared__ double2 sh2[WG];
+    int64_t g, rb;
+    if (!xcd_group_block(s.nblk, (s.K + RB - 1) / RB, g, rb)) return;
+    const int64_t j0 = g * RB;
+    bool run[RB];
+    SeedState st[RB];
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        run[b] = j0 + b < s.K;
+        if (run[b]) {
+            st[b] = s.seed[j0 + b];
+            run[b] = seed_running(st[b], s.TB);
+        }
+        any |= run[b];
+    }
+    if (!any) return;
+    const RhsDesc d = s.desc[j0];
     const int lane = threadIdx.x & 63;
-    const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t slice = rb * 4 + (threadIdx.x >> 6);
     const int64_t row = slice * 64 + lane;
-    const int par = st.iter & 1;
-    const double2 *pold = p_buf(s, d, par ^ 1);
-    double2 *pnew = p_buf(s, d, par);
-    const double2 *r = ring_slot(s, (st.base + st.step) % (s.TB + 1), d);
-    const double2 b = st.beta_prev;
-    double2 pq = cmk(0, 0);
+    const double2 *pv[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) pv[b] = s.p + (run[b] ? s.desc[j0 + b].voff : d.voff);
+    double ax[RB], ay[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        ax[b] = 0;
+        ay[b] = 0;
+    }
     if (slice < d.nslices) {
         const int64_t off = d.slice_ptr[slice];
         const int w = d.slice_w[slice];
-        double ax = 0, ay = 0;
         for (int k = 0; k < w; ++k) {
             const int c = d.ell_col[off + (int64_t)k * 64 + lane];
             const double v = d.ell_val[off + (int64_t)k * 64 + lane];
-            const double2 pc = cfma(b, pold[c], r[c]);
-            ax = fma(v, pc.x, ax);
-            ay = fma(v, pc.y, ay);
-        }
-        if (row < d.n) {
-            const double2 pr = cfma(b, pold[row], r[row]);
-            pnew[row] = pr;
-            const double2 qv = cfma(st.zs, pr, make_double2(-ax, -ay));
-            s.q[d.voff + row] = qv;
-            pq = cmul(pr, qv);
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                if (run[b]) {
+                    const double2 pc = pv[b][c];
+                    ax[b] = fma(v, pc.x, ax[b]);
+                    ay[b] = fma(v, pc.y, ay[b]);
+                }
+            }
         }
     }
-    pq = block_sum2(pq, sh2);
-    if (threadIdx.x == 0) s.part2[j * s.nblk + blockIdx.x] = pq;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        double2 pq = cmk(0, 0);
+        if (run[b] && slice < d.nslices && row < d.n) {
+            const double2 pr = pv[b][row];
+            const double2 qv = cfma(st[b].zs, pr, make_double2(-ax[b], -ay[b]));
+            s.q[s.desc[j0 + b].voff + row] = qv;
+            pq = cmul(pr, qv);
+        }
+        if (run[b]) {  // uniform across the workgroup
+            pq = block_sum2(pq, sh2);
+            if (threadIdx.x == 0) s.part2[(j0 + b) * s.nblk + rb] = pq;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(WG) k_alpha(SolveDev s)
@@ -421,112 +456,6 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
 }
 
 // ---------------------------------------------------------------------------------------
-// Deferred per-shift update.  For every active pair and every step t < nact of the block
-//   u_k <- r_t + b'_t u_k ;  x_k <- x_k + a'_t u_k
-// x_k and u_k stay in registers across the block, so each is read and written once per
-// block instead of once per iteration.  One thread per row; a workgroup covers 256 rows of
-// one rhs and `G` shifts, NP pairs in flight per thread.  Coefficients and step counts are
-// uniform across the workgroup (scalar loads).  x_k and u_k are streamed with nontemporal
-// loads and stores: they are not reused before the next block.
-// ---------------------------------------------------------------------------------------
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f2v __attribute__((ext_vector_type(2)));
-
-__device__ inline double2 ld_nt(const double2 *p)
-{
-    const d2v v = __builtin_nontemporal_load((const d2v *)p);
-    return make_double2(v.x, v.y);
-}
-__device__ inline float2 ld_nt(const float2 *p)
-{
-    const f2v v = __builtin_nontemporal_load((const f2v *)p);
-    return make_float2(v.x, v.y);
-}
-__device__ inline void st_nt(double2 *p, double2 v)
-{
-    const d2v w = {v.x, v.y};
-    __builtin_nontemporal_store(w, (d2v *)p);
-}
-__device__ inline void st_nt(float2 *p, float2 v)
-{
-    const f2v w = {v.x, v.y};
-    __builtin_nontemporal_store(w, (f2v *)p);
-}
-
-template <int TB, typename V, int NP, bool PROJ>
-__global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed, const double2 *__restrict__ ring,
-                                              const V *__restrict__ coef, const int32_t *__restrict__ nact,
-                                              V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
-                                              const int64_t *__restrict__ proj_row,
-                                              const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
-                                              int ngroups)
-{
-    const int64_t j = blockIdx.y / ngroups;
-    const int g = blockIdx.y % ngroups;
-    const int ns = seed[j].step;
-    if (ns == 0) return;
-    const int base = seed[j].base;
-    const bool fresh = seed[j].iter == ns;
-    const int64_t n = desc[j].n;
-    const int64_t voff = desc[j].voff;
-    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (row >= n) return;
-    V r[TB];
-#pragma unroll
-    for (int t = 0; t < TB; ++t) {
-        if (t < ns) r[t] = to_v<V>(ring[(int64_t)((base + t) % (TB + 1)) * ntot + voff + row]);
-        else r[t] = to_v<V>(cmk(0, 0));
-    }
-    X += M * voff;
-    P += M * voff;
-    const int64_t k0 = (int64_t)g * G;
-    const int64_t k1 = min(k0 + G, M);
-    const int64_t prow = PROJ ? proj_row[j] : -1;
-    for (int64_t k = k0; k < k1; k += NP) {
-        V x[NP], u[NP];
-        int na[NP];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const int64_t pair = j * M + k + q;
-            na[q] = (k + q < k1) ? nact[pair] : 0;
-            x[q] = to_v<V>(cmk(0, 0));
-            u[q] = x[q];
-            if (na[q] > 0 && !fresh) {
-                u[q] = ld_nt(P + (k + q) * n + row);
-                if (PROJ) {
-                    if (row == prow) x[q] = to_v<V>(Xproj[pair]);
-                } else {
-                    x[q] = ld_nt(X + (k + q) * n + row);
-                }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                if (t < na[q]) {
-                    const V *cf = coef + ((j * M + k + q) * TB + t) * 2;
-                    u[q] = cfma(cf[1], u[q], r[t]);
-                    x[q] = cfma(cf[0], u[q], x[q]);
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const int64_t pair = j * M + k + q;
-            if (na[q] > 0) {
-                st_nt(P + (k + q) * n + row, u[q]);
-                if (PROJ) {
-                    if (row == prow) Xproj[pair] = make_double2((double)x[q].x, (double)x[q].y);
-                } else {
-                    st_nt(X + (k + q) * n + row, x[q]);
-                }
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------------------
 // End of block, one workgroup per rhs: stop / switch decisions (Sec. 3.3 seed switching).
 // The new seed t is the active shift with the largest residual (lowest index on ties);
 // pi_k <- pi_k / pi_t, pi_{k,prev} <- pi_{k,prev} / pi_{t,prev}, alpha_prev <- alpha^t_n,
@@ -666,7 +595,7 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
             V *up = P + k * d.n + row;
             const V u = cfma(sc, *up, zero);
             *up = u;
-            if (k == st.sw_target) p_buf(s, d, (st.iter + 1) & 1)[row] = make_double2((double)u.x, (double)u.y);
+            if (k == st.sw_target) p_buf(s, d, 0)[row] = make_double2((double)u.x, (double)u.y);
         }
         rr = cmul(r, r);
     }
@@ -894,7 +823,12 @@ hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_
 
 hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pspmv, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    hipLaunchKernelGGL(k_pupd, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    const int RB = s.spmv_rb;
+    const int64_t G = (s.K + RB - 1) / RB;
+    const int64_t nwg = G < 8 ? s.nblk * G : s.nblk * 8 * ((G + 7) / 8);
+    if (RB == 2) hipLaunchKernelGGL(k_spmv<2>, dim3((unsigned)nwg), dim3(WG), 0, st, s);
+    else hipLaunchKernelGGL(k_spmv<1>, dim3((unsigned)nwg), dim3(WG), 0, st, s);
     hipLaunchKernelGGL(k_alpha, dim3((unsigned)s.K), dim3(WG), 0, st, s);
     hipLaunchKernelGGL(k_rupd, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
     hipLaunchKernelGGL(k_beta, dim3((unsigned)s.K), dim3(WG), 0, st, s);
@@ -908,41 +842,6 @@ hipError_t launch_pair_scalars(const SolveDev &s, hipStream_t st)
     if (s.precision == 0) hipLaunchKernelGGL(k_pair_scalars<double2>, g, dim3(WG), 0, st, s);
     else hipLaunchKernelGGL(k_pair_scalars<float2>, g, dim3(WG), 0, st, s);
     return hipGetLastError();
-}
-
-template <int TB, typename V, int NP>
-static hipError_t flush_v(const SolveDev &s, hipStream_t st)
-{
-    const int G = s.shifts_per_wg;
-    const int ng = (int)((s.M + G - 1) / G);
-    const dim3 g = grid2(s.nblk, s.K * ng);
-    const V *coef = (const V *)s.coef;
-    if (s.Xproj)
-        hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)nullptr,
-                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng);
-    else
-        hipLaunchKernelGGL((k_flush<TB, V, NP, false>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)s.X,
-                           (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng);
-    return hipGetLastError();
-}
-
-template <int TB>
-static hipError_t flush_tb(const SolveDev &s, hipStream_t st)
-{
-    if (s.precision == 0) return flush_v<TB, double2, 2>(s, st);
-    return flush_v<TB, float2, 4>(s, st);
-}
-
-hipError_t launch_flush(const SolveDev &s, hipStream_t st)
-{
-    switch (s.TB) {
-    case 1: return flush_tb<1>(s, st);
-    case 2: return flush_tb<2>(s, st);
-    case 4: return flush_tb<4>(s, st);
-    case 8: return flush_tb<8>(s, st);
-    case 16: return flush_tb<16>(s, st);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_block_finalize(const SolveDev &s, hipStream_t st)

@@ -130,6 +130,7 @@ struct SolveDev {
     int64_t nblk;              // row blocks of 256
     int shifts_per_wg;
     int zper;                  // 1: one shift per rhs (M = 1, z has K entries), used by refinement
+    int spmv_rb;               // right-hand sides per SpMV thread (2 needs one shared matrix)
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
 };
 
