@@ -345,8 +345,8 @@ int solve(SolveRequest &rq, hipStream_t st)
     // 16 iterations per deferred update: the update streams x_k, u_k at copy bandwidth and
     // its arithmetic (8 fused multiply-adds per step) still hides under the memory time
     int TB = o.block > 0 ? o.block : 16;
-    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16)
-        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8 or 16");
+    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16 && TB != 32)
+        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8, 16 or 32");
     int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 32);
     std::vector<int32_t> seeds(K, 0);
     for (int64_t j = 0; j < K; ++j) {

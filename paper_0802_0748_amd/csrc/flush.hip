@@ -142,6 +142,7 @@ hipError_t launch_flush(const SolveDev &s, hipStream_t st)
     case 4: return flush_tb<4>(s, st);
     case 8: return flush_tb<8>(s, st);
     case 16: return flush_tb<16>(s, st);
+    case 32: return flush_tb<32>(s, st);
     default: return hipErrorInvalidValue;
     }
 }
