@@ -154,11 +154,11 @@ def run_variants(S, torch, n_rhs):
 
     Xb, t_b = timed(lambda: S.shifted_cocg_solve(H, p.z, B, **base)[0])
     ref = Xb.cpu().numpy()
-    out["batched fp64, block 16"] = (t_b, 0.0)
+    out["batched fp64, block 24"] = (t_b, 0.0)
     forms = [("one rhs at a time, fp64, update every iteration (plain)", dict(block=1), 1),
-             ("one rhs at a time, fp64, block 16", dict(block=16), 1),
-             ("batched fp32 storage, block 16", dict(block=16, precision="fp32"), K),
-             ("batched fp32 storage + fp64 refinement", dict(block=16, precision="fp32", refine=2), K)]
+             ("one rhs at a time, fp64, block 24", dict(block=24), 1),
+             ("batched fp32 storage, block 24", dict(block=24, precision="fp32"), K),
+             ("batched fp32 storage + fp64 refinement", dict(block=24, precision="fp32", refine=2), K)]
     for name, extra, per in forms:
         X = np.zeros_like(ref)
         t = 0.0
@@ -253,7 +253,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}",
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
-                   "block": args.block or 16, "iterations_per_step": int(np.max(iters))},
+                   "block": args.block or 24, "iterations_per_step": int(np.max(iters))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_flush (deferred per-shift update)",

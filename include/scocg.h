@@ -55,7 +55,7 @@ typedef struct {
     int32_t seed_index;     /* initial seed shift; -1: smallest Im z, then Re z nearest Tr(H)/n, then lowest index */
     int32_t seed_switching; /* 1: switch seed when it converges (Sec. 3.3) */
     int32_t fixed_iter;     /* > 0: run exactly this many iterations, no freezing, no switching */
-    int32_t block;          /* iterations per deferred shift update (1,2,4,8,16); 0 = automatic */
+    int32_t block;          /* iterations per deferred shift update (1,2,4,8,16,24,32); 0 = automatic (24) */
     int32_t shifts_per_wg;  /* shifts one workgroup updates in the deferred update; 0 = automatic */
     int32_t check_true;     /* 1: compute the FP64 true residual of every pair into the report */
     int32_t keep_tape;      /* 1: keep the solutions for backward() */

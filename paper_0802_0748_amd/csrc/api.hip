@@ -342,11 +342,12 @@ int solve(SolveRequest &rq, hipStream_t st)
     for (int64_t k = 0; k < nz; ++k)
         if (!std::isfinite(rq.z[2 * k]) || !std::isfinite(rq.z[2 * k + 1]))
             return fail(SCOCG_EINVAL, "non-finite shift");
-    // 16 iterations per deferred update: the update streams x_k, u_k at copy bandwidth and
-    // its arithmetic (8 fused multiply-adds per step) still hides under the memory time
-    int TB = o.block > 0 ? o.block : 16;
-    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16 && TB != 32)
-        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8, 16 or 32");
+    // 24 iterations per deferred update: the update streams x_k, u_k at copy bandwidth and
+    // its arithmetic (8 fused multiply-adds per step) still hides under the memory time;
+    // longer blocks hold the residual history in so many registers that occupancy drops
+    int TB = o.block > 0 ? o.block : 24;
+    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16 && TB != 24 && TB != 32)
+        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8, 16, 24 or 32");
     int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 32);
     std::vector<int32_t> seeds(K, 0);
     for (int64_t j = 0; j < K; ++j) {

@@ -8,9 +8,12 @@ namespace scocg {
 //   u_k <- r_t + b'_t u_k ;  x_k <- x_k + a'_t u_k
 // x_k and u_k stay in registers across the block, so each is read and written once per
 // block instead of once per iteration.  One thread per row; a workgroup covers 256 rows of
-// one rhs and `G` shifts, NP pairs in flight per thread.  Coefficients and step counts are
-// uniform across the workgroup (scalar loads).  x_k and u_k are streamed with nontemporal
-// loads and stores: they are not reused before the next block.
+// one rhs and `G` shifts, NP pairs in flight per thread.  Every step runs for every pair:
+// the coefficient table pads a pair's steps past its last one with a' = 0, b' = 1 and the
+// residual history is zero past the block's last step, so those steps leave x_k (and u_k)
+// as they are; the only branches left are uniform ones over whole pair groups.
+// Coefficients are uniform across the workgroup (scalar loads).  x_k and u_k are streamed
+// with nontemporal loads and stores: they are not reused before the next block.
 // ---------------------------------------------------------------------------------------
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
@@ -34,6 +37,26 @@ __device__ inline void st_nt(float2 *p, float2 v)
 {
     const f2v w = {v.x, v.y};
     __builtin_nontemporal_store(w, (f2v *)p);
+}
+
+// Projection mode: TB steps for the NP pairs k .. k+NP-1 (of those below k1) held in
+// registers, with or without the x_k update; pair p's (a', b') table starts at
+// coef + p * TB * 2.
+template <int TB, typename V, int NP, bool WITH_X>
+__device__ inline void apply_steps(const V *coef, int64_t pair0, int64_t k, int64_t k1, const V (&r)[TB],
+                                   V (&x)[NP], V (&u)[NP])
+{
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            // a slot past the group's end reuses the first pair's table (its result is not stored)
+            const int64_t kq = (k + q < k1) ? k + q : k;
+            const V *cf = coef + ((pair0 + kq) * TB + t) * 2;
+            u[q] = cfma(cf[1], u[q], r[t]);
+            if (WITH_X) x[q] = cfma(cf[0], u[q], x[q]);
+        }
+    }
 }
 
 template <int TB, typename V, int NP, bool PROJ>
@@ -65,13 +88,18 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     const int64_t k0 = (int64_t)g * G;
     const int64_t k1 = min(k0 + G, M);
     const int64_t prow = PROJ ? proj_row[j] : -1;
+    // projection mode needs x_k only in the workgroup that holds the kept row (uniform test)
+    const int64_t row0 = (int64_t)blockIdx.x * WG;
+    const bool with_x = !PROJ || (prow >= row0 && prow < row0 + WG);
     for (int64_t k = k0; k < k1; k += NP) {
         V x[NP], u[NP];
         int na[NP];
+        bool any = false;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
             const int64_t pair = j * M + k + q;
             na[q] = (k + q < k1) ? nact[pair] : 0;
+            any = any || na[q] > 0;
             x[q] = to_v<V>(cmk(0, 0));
             u[q] = x[q];
             if (na[q] > 0 && !fresh) {
@@ -83,16 +111,24 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
                 }
             }
         }
+        if (!any) continue;
+        if constexpr (!PROJ) {
+            // the same steps as apply_steps, written out: this form compiles to fewer
+            // registers (121 against 147 VGPRs for FP64 and 24 steps: one more wave per SIMD)
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
+            for (int t = 0; t < TB; ++t) {
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                if (t < na[q]) {
-                    const V *cf = coef + ((j * M + k + q) * TB + t) * 2;
+                for (int q = 0; q < NP; ++q) {
+                    // a slot past the group's end reuses the first pair's table (not stored)
+                    const int64_t kq = (k + q < k1) ? k + q : k;
+                    const V *cf = coef + ((j * M + kq) * TB + t) * 2;
                     u[q] = cfma(cf[1], u[q], r[t]);
                     x[q] = cfma(cf[0], u[q], x[q]);
                 }
             }
+        } else {
+            if (with_x) apply_steps<TB, V, NP, true>(coef, j * M, k, k1, r, x, u);
+            else apply_steps<TB, V, NP, false>(coef, j * M, k, k1, r, x, u);
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
@@ -127,11 +163,13 @@ static hipError_t flush_v(const SolveDev &s, hipStream_t st)
     return hipGetLastError();
 }
 
+// Pairs in flight per thread: the residual history takes 4 (FP64) or 2 (FP32) registers per
+// step, so long blocks keep fewer pairs in flight to hold the occupancy.
 template <int TB>
 static hipError_t flush_tb(const SolveDev &s, hipStream_t st)
 {
-    if (s.precision == 0) return flush_v<TB, double2, 2>(s, st);
-    return flush_v<TB, float2, 4>(s, st);
+    if (s.precision == 0) return flush_v<TB, double2, (TB <= 16 ? 2 : 1)>(s, st);
+    return flush_v<TB, float2, (TB <= 16 ? 4 : 2)>(s, st);
 }
 
 hipError_t launch_flush(const SolveDev &s, hipStream_t st)
@@ -142,6 +180,7 @@ hipError_t launch_flush(const SolveDev &s, hipStream_t st)
     case 4: return flush_tb<4>(s, st);
     case 8: return flush_tb<8>(s, st);
     case 16: return flush_tb<16>(s, st);
+    case 24: return flush_tb<24>(s, st);
     case 32: return flush_tb<32>(s, st);
     default: return hipErrorInvalidValue;
     }

@@ -424,6 +424,13 @@ __device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t
     s.active[pair] = act;
     s.nact[pair] = na;
     if (na == 0) return 0ull;
+    // Steps past the pair's last one are padded with a' = 0, b' = 1, which leaves x_k
+    // unchanged (and u_k too while the residual history is zero there), so the deferred
+    // update runs every step without a per-pair branch.
+    for (int t = na; t < s.TB; ++t) {
+        cf[2 * t + 0] = to_v<V>(cmk(0, 0));
+        cf[2 * t + 1] = to_v<V>(cmk(1, 0));
+    }
     // algorithmic bytes of this pair's deferred update: u_k (and x_k unless projected)
     // written once, and read once unless this is the first block
     const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;

@@ -17,7 +17,7 @@ import torch
 from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scocg", "tune.json")
-BLOCKS = (4, 8, 16)
+BLOCKS = (8, 16, 24, 32)
 SHIFTS_PER_WG = (16, 32, 64)
 
 

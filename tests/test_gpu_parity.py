@@ -53,13 +53,34 @@ def test_block_length_does_not_change_bits():
     H = S.Hamiltonian.from_csr(Hc)
     Bt = torch.from_numpy(B).cuda()
     ref = None
-    for tb in (1, 2, 4, 8, 16):
+    for tb in (1, 2, 4, 8, 16, 24, 32):
         X, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=37, seed_index=0, block=tb)
         Xn = X.cpu().numpy()
         if ref is None:
             ref = Xn
         else:
             assert np.array_equal(Xn, ref), tb
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_block_length_does_not_change_bits_with_freezing_and_switching(precision):
+    """Pairs freeze inside a block and seeds switch: the padded steps of the deferred update
+    leave frozen solutions untouched, so every block length gives the same bits."""
+    S = _S()
+    Hc, z, B = _problem(300, 3)
+    H = S.Hamiltonian.from_csr(Hc)
+    Bt = torch.from_numpy(B).cuda()
+    ref = None
+    for tb in (1, 8, 24, 32):
+        X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision, block=tb)
+        assert rc == 0
+        assert S.last_timing()["switches"] > 0
+        cur = (X.cpu().numpy(), rep["iters"].copy())
+        if ref is None:
+            ref = cur
+        else:
+            assert np.array_equal(cur[1], ref[1]), tb
+            assert np.array_equal(cur[0], ref[0]), tb
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
