@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "shift\u00d7RHS solves/sec to rel. residual 1e-8; SpMV achieved HBM GB/s vs peak"
 UPDATE_KERNEL_SOURCES = ["flush.hip", "device_common.h", "scocg_internal.h"]
 
 
@@ -51,6 +52,13 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=8000)
     ap.add_argument("--variants", type=int, default=0,
                     help="also compare solver forms on the diamond problem with this many rhs (stderr)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 2 GiB device to device once (reference for the HBM byte counters)")
+    ap.add_argument("--pmc-summary", nargs=6, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR",
+                                                       "BENCH_JSON", "COMMANDS_TXT"),
+                    help="write profiles/k_flush_<workload>_traffic.{json,md} from rocprofv3 counter runs")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("STATS_DIR", "BENCH_JSON", "COMMAND_TXT"),
+                    help="write profiles/kernels_<workload>_stats.md from a rocprofv3 --stats run")
     return ap.parse_args()
 
 
@@ -78,6 +86,162 @@ def measured_traffic(workload):
     if rec.get("kernel_sources_sha1") != digest:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+COPY_BYTES = 2 ** 31
+
+
+def copy_calibration():
+    """One device-to-device copy of 2 GiB: the HBM byte counters read on it give the factor
+    from counter units to bytes."""
+    import torch
+
+    x = torch.ones(COPY_BYTES // 16, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"[bench] copied {COPY_BYTES} bytes", file=sys.stderr, flush=True)
+    return 0
+
+
+def _read_csv(path):
+    import csv
+
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _find_csv(d, suffix):
+    for root, _, files in os.walk(d):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def _bench_line(path):
+    with open(path) as f:
+        for ln in f:
+            ln = ln.strip()
+            if ln.startswith("{"):
+                return json.loads(ln)
+    raise ValueError(f"no JSON line in {path}")
+
+
+def _main_update_dispatches(rows):
+    """Counter rows of the benchmark solve's update kernel: the k_flush instance with the most
+    dispatches, restricted to its largest grid (the small warm-up solve has a smaller one)."""
+    rows = [r for r in rows if "k_flush" in r["Kernel_Name"]]
+    by_name = {}
+    for r in rows:
+        by_name.setdefault(r["Kernel_Name"], []).append(r)
+    name, rs = max(by_name.items(), key=lambda kv: len(kv[1]))
+
+    def grid(r):
+        if r.get("Grid_Size"):
+            return int(r["Grid_Size"])
+        return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+
+    gmax = max(grid(r) for r in rs)
+    return name, [r for r in rs if grid(r) == gmax]
+
+
+def pmc_summary(args):
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir, bench_json, commands_txt = args.pmc_summary
+    line = _bench_line(bench_json)
+    algo = line["roofline"]["bytes_per_launch"]
+    name, fr = _main_update_dispatches(_read_csv(_find_csv(fetch_dir, "counter_collection.csv")))
+    _, wr = _main_update_dispatches(_read_csv(_find_csv(write_dir, "counter_collection.csv")))
+    fetch_kib = sum(float(r["Counter_Value"]) for r in fr) / len(fr)
+    write_kib = sum(float(r["Counter_Value"]) for r in wr) / len(wr)
+
+    def copy_kib(d):
+        rows = [r for r in _read_csv(_find_csv(d, "counter_collection.csv")) if "copyBuffer" in r["Kernel_Name"]]
+        return max(float(r["Counter_Value"]) for r in rows)
+
+    cf, cw = copy_kib(cfetch_dir), copy_kib(cwrite_dir)
+    # a copy of COPY_BYTES reads and writes COPY_BYTES each
+    fscale, wscale = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
+    rd, wb = fetch_kib * 1024 * fscale, write_kib * 1024 * wscale
+    with open(commands_txt) as f:
+        commands = [c.strip() for c in f if c.strip()]
+    rec = {"kernel": name.split("(")[0].replace("void ", ""), "workload": line["config"]["workload"],
+           "launches": len(fr), "fetch_kib_per_launch": fetch_kib, "write_kib_per_launch": write_kib,
+           "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw, "fetch_scale": fscale,
+                                "write_scale": wscale},
+           "hbm_bytes_per_launch": rd + wb, "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wb,
+           "algorithmic_bytes_per_launch": algo, "ratio": (rd + wb) / algo, "commands": commands,
+           "kernel_sources_sha1": update_kernel_digest(),
+           "kernel_sources": [f"paper_0802_0748_amd/csrc/{n}" for n in UPDATE_KERNEL_SOURCES]}
+    out = os.path.join(ROOT, "profiles", f"k_flush_{args.workload}_traffic")
+    with open(out + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    cmd_block = "\n".join(commands)
+    md = f"""# HBM traffic of the deferred per-shift update ({args.workload} workload)
+
+Kernel `{rec['kernel']}`, {rec['workload']}. Counters per dispatch from two rocprofv3 runs, averaged
+over the {len(fr)} launches of the benchmark solve (the small warm-up solve is excluded by grid size),
+and a plain 2 GiB device copy for calibration (`bench.py --copy-calibration`):
+
+```
+{cmd_block}
+```
+
+| counter | copy of 2 GiB (KiB) | bytes per KiB | k_flush per launch (KiB) | k_flush per launch (GB) |
+|---|---:|---:|---:|---:|
+| FETCH_SIZE | {cf:.0f} | {fscale * 1024:.1f} | {fetch_kib:.0f} | {rd / 1e9:.2f} |
+| WRITE_SIZE | {cw:.0f} | {wscale * 1024:.1f} | {write_kib:.0f} | {wb / 1e9:.2f} |
+
+Measured HBM traffic per launch: **{(rd + wb) / 1e9:.2f} GB**; algorithmic bytes per launch (x_k and u_k read
+and written once for every active pair, the residual history read once per rhs, counted on the device):
+**{algo / 1e9:.2f} GB**; ratio {(rd + wb) / algo:.3f}.
+
+Kernel sources: {', '.join(UPDATE_KERNEL_SOURCES)} (under paper_0802_0748_amd/csrc), sha1
+`{rec['kernel_sources_sha1']}`; bench.py reports this traffic only while these sources are unchanged.
+"""
+    with open(out + ".md", "w") as f:
+        f.write(md)
+    print(f"[bench] wrote {out}.json/.md: {(rd + wb) / 1e9:.2f} GB per launch, ratio {(rd + wb) / algo:.3f}",
+          file=sys.stderr)
+    return 0
+
+
+def trace_summary(args):
+    stats_dir, bench_json, command_txt = args.trace_summary
+    line = _bench_line(bench_json)
+    rows = _read_csv(_find_csv(stats_dir, "kernel_stats.csv"))
+    with open(command_txt) as f:
+        command = f.read().strip()
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = os.path.join(ROOT, "profiles", f"kernels_{args.workload}_stats.md")
+    lines = [f"# Kernel time, {args.workload} benchmark workload", "",
+             f"{line['config']['workload']}; bench.py reported {line['value']:.1f} {line['unit']} "
+             f"({line['ms_per_step'] / 1e3:.2f} s per solve) in this profiled run.", "",
+             "```", command, "```", "",
+             "| kernel | calls | total ms | average us | share |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:14]:
+        nm = r["Name"].split("(")[0].replace("void ", "").replace("HIP_vector_type<double, 2u>", "double2")
+        nm = nm.replace("HIP_vector_type<float, 2u>", "float2")
+        lines.append(f"| `{nm}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} % |")
+    try:
+        trace = _read_csv(_find_csv(stats_dir, "kernel_trace.csv"))
+    except FileNotFoundError:
+        trace = []
+    if trace:
+        # the benchmark solve's update launches: the busiest k_flush instance at its largest grid
+        name, disp = _main_update_dispatches(trace)
+        avg_ms = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in disp) / len(disp) / 1e6
+        lines += ["", f"Deferred update `{name.split('(')[0].replace('void ', '')}`: rocprofv3 average "
+                      f"{avg_ms:.3f} ms per launch over the {len(disp)} launches of the benchmark solves; "
+                      f"bench.py's HIP-event average over the same solves: {line['roofline']['avg_launch_ms']:.3f} ms "
+                      f"({line['roofline']['bytes_per_launch'] / 1e9:.2f} GB algorithmic per launch, "
+                      f"{line['roofline']['achieved']:.0f} GB/s)."]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"[bench] wrote {out}", file=sys.stderr)
+    return 0
 
 
 def cpu_baseline(p, gpu_iters, sample_iters):
@@ -177,6 +341,12 @@ def run_variants(S, torch, n_rhs):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        return pmc_summary(args)
+    if args.trace_summary:
+        return trace_summary(args)
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               "(the solver runs on a single device).", file=sys.stderr)
@@ -239,7 +409,7 @@ def main():
     value = converged / elapsed
     achieved = (upd_bytes / 1e9) / (upd_ms / 1e3) if upd_ms > 0 else 0.0
     line = {
-        "metric": "shift x RHS solves/sec to rel. residual 1e-8",
+        "metric": METRIC,
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,

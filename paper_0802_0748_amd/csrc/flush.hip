@@ -77,6 +77,12 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     const int64_t voff = desc[j].voff;
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (row >= n) return;
+    const int64_t k0 = (int64_t)g * G;
+    const int64_t k1 = min(k0 + G, M);
+    // late in a solve most shift groups are frozen: skip them before reading the history
+    bool group_active = false;
+    for (int64_t k = k0; k < k1; ++k) group_active = group_active || nact[j * M + k] > 0;
+    if (!group_active) return;
     V r[TB];
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
@@ -85,8 +91,6 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     }
     X += M * voff;
     P += M * voff;
-    const int64_t k0 = (int64_t)g * G;
-    const int64_t k1 = min(k0 + G, M);
     const int64_t prow = PROJ ? proj_row[j] : -1;
     // projection mode needs x_k only in the workgroup that holds the kept row (uniform test)
     const int64_t row0 = (int64_t)blockIdx.x * WG;
