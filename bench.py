@@ -12,8 +12,10 @@ deferred per-shift update, timed with HIP events on its stream) and the FP64 CPU
 oracle timed on a bounded sample of the same workload.
 
 Other workloads (--workload): `cubic` (16^3 lattice, 64 shifts, G_00 to 1e-10, the
-latency-bound case) and `hubbard` (extended Hubbard ring, 11,778,624 rows, 128 shifts,
-one complex right-hand side).  --variants prints, on stderr, the same diamond problem
+latency-bound case), `hubbard` (extended Hubbard ring, 11,778,624 rows, 128 shifts,
+one complex right-hand side) and `batch` (--problems disordered cubic lattices of
+uneven size, 32 unit RHS each, 512 shifts eta = 0.002, FP32 directions, one batched
+solve).  --variants prints, on stderr, the same diamond problem
 at a reduced number of right-hand sides solved by the plain FP64 path (one rhs at a
 time, shift vectors updated every iteration), by the blocked update, batched, and with
 FP32 storage, with the error of each against the FP64 batched result.
@@ -40,11 +42,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="diamond", choices=["diamond", "cubic", "hubbard"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--workload", default="diamond", choices=["diamond", "cubic", "hubbard", "batch"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
+                    help="default fp64 (fp32 storage for the batch workload)")
+    ap.add_argument("--problems", type=int, default=8, help="lattices in the batch workload")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--shifts-per-wg", type=int, default=0)
-    ap.add_argument("--n-rhs", type=int, default=256)
+    ap.add_argument("--n-rhs", type=int, default=0, help="default 256 (diamond), 32 per lattice (batch)")
     ap.add_argument("--n-shift", type=int, default=0)
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--tol", type=float, default=0.0)
@@ -244,10 +248,11 @@ def trace_summary(args):
     return 0
 
 
-def cpu_baseline(p, gpu_iters, sample_iters):
+def cpu_baseline(p, gpu_iters, sample_iters, row_scale=None, converged=None):
     """Time the oracle on one right-hand side with all shifts for a fixed number of
     iterations (and with a single shift, to separate the seed cost), then scale to
-    the whole workload with the per-pair iteration counts of the GPU solve."""
+    the whole workload with the per-pair iteration counts of the GPU solve (and, for
+    right-hand sides of other sizes, by their row count relative to this one)."""
     from oracle import oracle as O
 
     b = p.rhs_dense()[0]
@@ -261,22 +266,24 @@ def cpu_baseline(p, gpu_iters, sample_iters):
     M = len(p.z)
     c_seed = t_one / sample_iters
     c_pair = max(t_all - t_one, 0.0) / ((M - 1) * sample_iters)
+    scale = np.ones(gpu_iters.shape[0]) if row_scale is None else np.asarray(row_scale, dtype=float)
     seed_iters = gpu_iters.max(axis=1).sum()
-    est = c_seed * seed_iters + c_pair * gpu_iters.sum()
-    converged = gpu_iters.size
+    est = float(np.sum(scale * (c_seed * gpu_iters.max(axis=1) + c_pair * gpu_iters.sum(axis=1))))
+    if converged is None:
+        converged = gpu_iters.size
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=converged / est, unit="solves/s", cores=threads, kind="oracle",
                 sample=(f"oracle on the first rhs with all {M} shifts for {sample_iters} fixed iterations "
                         f"({t_all:.1f} s) and with one shift ({t_one:.1f} s); per-pair and per-seed iteration "
                         f"costs scaled by the GPU solve's iteration counts (sum {int(gpu_iters.sum())} pair-"
-                        f"iterations, {int(seed_iters)} seed iterations) to an estimated {est:.0f} s"))
+                        f"iterations, {int(seed_iters)} seed iterations) to an estimated {est:.3g} s"))
 
 
 def load_workload(args):
     from workloads import config1_cubic, config2_diamond, config3_hubbard
 
     if args.workload == "diamond":
-        p = config2_diamond(n_shift=args.n_shift or 256, n_rhs=args.n_rhs)
+        p = config2_diamond(n_shift=args.n_shift or 256, n_rhs=args.n_rhs or 256)
         p.max_iter, p.tol = 40000, 1e-8
         desc = (f"diamond 8x8x8 cells, 4 orbitals/atom (n={p.H.n}, nnz={p.H.nnz}), {len(p.z)} shifts eta=0.005, "
                 f"{p.n_rhs} unit RHS")
@@ -294,6 +301,80 @@ def load_workload(args):
     if args.tol:
         p.tol = args.tol
     return p, desc
+
+
+def update_roofline(upd_ms, upd_bytes, upd_launches, workload):
+    achieved = (upd_bytes / 1e9) / (upd_ms / 1e3) if upd_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload),
+            "kernel": "k_flush (deferred per-shift update)",
+            "avg_launch_ms": upd_ms / max(upd_launches, 1),
+            "bytes_per_launch": upd_bytes / max(upd_launches, 1)}
+
+
+def bench_batch(args, S, torch):
+    """Disordered cubic lattices of uneven size (L in 24..64, W in {1, 4, 8}), 32 unit RHS per
+    lattice, 512 shifts eta = 0.002, FP32 directions / FP64 scalars, all in one solve
+    (greens_diag_batched: one seed SpMV and one update launch per block for every lattice)."""
+    from workloads import config5_batch
+
+    prec = args.precision or "fp32"
+    probs = config5_batch(n_problems=args.problems, n_rhs=args.n_rhs or 32, n_shift=args.n_shift or 512)
+    tol, max_iter = args.tol or 1e-8, args.max_iter or 20000
+    Hs = [S.Hamiltonian.from_csr(p.H) for p in probs]
+    z = probs[0].z
+    rhs = [p.rhs_idx for p in probs]
+    K = sum(len(r) for r in rhs)
+    M = len(z)
+    ntot = sum(p.H.n * len(p.rhs_idx) for p in probs)
+    esz = 8 if prec == "fp32" else 16
+    print(f"[bench] workload batch: {len(probs)} lattices L={[p.extra['L'] for p in probs]}, {K} rhs x {M} shifts, "
+          f"{prec}; directions {M * ntot * esz / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    opts = dict(tol=tol, max_iter=max_iter, precision=prec, block=args.block, shifts_per_wg=args.shifts_per_wg)
+    S.greens_diag_batched(Hs[:1], z[:4], [rhs[0][:1]], fixed_iter=32, precision=prec, block=args.block)
+    torch.cuda.synchronize()
+    S.set_profiling(True)
+    upd_ms = upd_bytes = 0.0
+    upd_launches = converged = 0
+    iters = None
+    t0 = time.perf_counter()
+    for st in range(args.steps):
+        ts = time.perf_counter()
+        _, reps, rc = S.greens_diag_batched(Hs, z, rhs, **opts)
+        t = S.last_timing()
+        upd_ms += t["update_ms"]
+        upd_bytes += t["update_bytes"]
+        upd_launches += t["update_launches"]
+        status = np.concatenate([r["status"] for r in reps], axis=0)
+        iters = np.concatenate([r["iters"] for r in reps], axis=0)
+        converged += int((status == 0).sum())
+        print(f"[bench] step {st}: {time.perf_counter() - ts:.2f} s rc={rc} converged {int((status == 0).sum())}/"
+              f"{K * M} seed iterations {t['iterations']} blocks {t['blocks']} switches {t['switches']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    S.set_profiling(False)
+    Ls = sorted(p.extra["L"] for p in probs)
+    line = {
+        "metric": METRIC, "value": converged / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32-storage/f64-scalars", "data": "synthetic",
+        "config": {"workload": (f"{len(probs)} disordered simple-cubic lattices L={Ls} (W in 1,4,8), "
+                                f"{K} unit RHS ({len(rhs[0])} per lattice), {M} shifts eta=0.002, tol {tol:g}, "
+                                f"max_iter {max_iter}, one batched solve"),
+                   "n": int(sum(p.H.n for p in probs)), "nnz": int(sum(p.H.nnz for p in probs)), "n_shift": M,
+                   "n_rhs": K, "precision": prec, "block": args.block or 24,
+                   "iterations_per_step": int(np.max(iters))},
+        "roofline": update_roofline(upd_ms, upd_bytes, upd_launches, "batch"),
+    }
+    if not args.no_cpu_baseline:
+        p0 = probs[0]
+        sample = max(10, min(100000, int(args.cpu_iters * 4194304 / (M * p0.H.n))))
+        scale = np.concatenate([[p.H.n / p0.H.n] * len(p.rhs_idx) for p in probs])
+        line["cpu_baseline"] = cpu_baseline(p0, iters, sample, row_scale=scale,
+                                            converged=int((status == 0).sum()))
+    return line
 
 
 def run_variants(S, torch, n_rhs):
@@ -358,6 +439,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args, S, torch)), flush=True)
+        return 0
+    args.precision = args.precision or "fp64"
     p, desc = load_workload(args)
     H = S.Hamiltonian.from_csr(p.H)
     K, M, n = p.n_rhs, len(p.z), p.H.n
@@ -407,7 +492,6 @@ def main():
     elapsed = time.perf_counter() - t0
     S.set_profiling(False)
     value = converged / elapsed
-    achieved = (upd_bytes / 1e9) / (upd_ms / 1e3) if upd_ms > 0 else 0.0
     line = {
         "metric": METRIC,
         "value": value,
@@ -424,11 +508,7 @@ def main():
         "config": {"workload": f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}",
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
                    "block": args.block or 24, "iterations_per_step": int(np.max(iters))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
-                     "kernel": "k_flush (deferred per-shift update)",
-                     "avg_launch_ms": upd_ms / max(upd_launches, 1),
-                     "bytes_per_launch": upd_bytes / max(upd_launches, 1)},
+        "roofline": update_roofline(upd_ms, upd_bytes, upd_launches, args.workload),
     }
     if not args.no_cpu_baseline:
         # the oracle's cost per iteration grows with shifts x rows: keep the sample near

@@ -477,6 +477,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     HIPCHK(launch_zero(bcnt.ptr, K * sizeof(uint32_t), st));
     HIPCHK(launch_zero(bstats.ptr, 2 * sizeof(unsigned long long), st));
     if (need_full) HIPCHK(launch_zero(s.X, (size_t)M * ntot * esz, st));
+    HIPCHK(launch_zero(s.p, 2 * vec * sizeof(double2), st));
     HIPCHK(launch_init(s, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, bsd.as<int32_t>(), limit, st));
 
     PinnedBuf host_state;

@@ -67,15 +67,20 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
                                               const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
                                               int ngroups)
 {
+    // Row blocks run fastest in dispatch order, so the concurrently running workgroups of one
+    // shift group stream long contiguous stretches of each pair's x and u.  (Dealing the shift
+    // groups of one row block to one XCD instead, to reuse the residual history from L2, made
+    // the launch slower: the x, u accesses then scatter over many DRAM pages.)
     const int64_t j = blockIdx.y / ngroups;
     const int g = blockIdx.y % ngroups;
+    const int64_t rb = blockIdx.x;
     const int ns = seed[j].step;
     if (ns == 0) return;
     const int base = seed[j].base;
     const bool fresh = seed[j].iter == ns;
     const int64_t n = desc[j].n;
     const int64_t voff = desc[j].voff;
-    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t row = rb * WG + threadIdx.x;
     if (row >= n) return;
     const int64_t k0 = (int64_t)g * G;
     const int64_t k1 = min(k0 + G, M);
@@ -93,7 +98,7 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     P += M * voff;
     const int64_t prow = PROJ ? proj_row[j] : -1;
     // projection mode needs x_k only in the workgroup that holds the kept row (uniform test)
-    const int64_t row0 = (int64_t)blockIdx.x * WG;
+    const int64_t row0 = rb * WG;
     const bool with_x = !PROJ || (prow >= row0 && prow < row0 + WG);
     for (int64_t k = k0; k < k1; k += NP) {
         V x[NP], u[NP];
@@ -149,14 +154,13 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     }
 }
 
-static inline dim3 flush_grid(int64_t x, int64_t y) { return dim3((unsigned)x, (unsigned)y, 1); }
-
 template <int TB, typename V, int NP>
 static hipError_t flush_v(const SolveDev &s, hipStream_t st)
 {
     const int G = s.shifts_per_wg;
     const int ng = (int)((s.M + G - 1) / G);
-    const dim3 g = flush_grid(s.nblk, s.K * ng);
+    if (s.K * ng > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const dim3 g((unsigned)s.nblk, (unsigned)(s.K * ng));
     const V *coef = (const V *)s.coef;
     if (s.Xproj)
         hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)nullptr,

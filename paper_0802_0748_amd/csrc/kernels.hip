@@ -3,7 +3,8 @@
 // flush.hip.
 //
 // Data layout in HBM (n rows, K right-hand sides, M shifts; see RhsDesc for mixed sizes):
-//   seed vectors r (ring of TB+1 slots), p (two parities), q : one contiguous vector per rhs
+//   seed vectors r (ring of TB+1 slots), q : one contiguous vector per rhs; p likewise, or
+//                                             two rhs interleaved (see p_index)
 //   per-shift vectors x_k, u_k                                : pair-major, FP64 or FP32 complex
 //   H : 64-row slices, each slice stored column-slot-major (slot k of the 64 rows is
 //       contiguous), FP64 values
@@ -68,21 +69,55 @@ __device__ inline bool arrive_last(uint32_t *cnt, int64_t j, uint32_t nblk)
     return last;
 }
 
-// Fixed-order sum of nblk complex partials (every thread participates, result in all threads).
+// Fixed-order sum of nblk complex partials (every thread participates, result in all threads):
+// thread t adds partials t, t + WG, t + 2 WG, ... in order, then the threads' sums are added
+// as a tree.  COHERENT: the partials were written by other workgroups of the same launch
+// (read past the caches with atomic loads); otherwise by an earlier launch (plain loads, which
+// the compiler can issue many at a time).
+// With plain loads a thread fetches 8 of its partials at a time (the sum order is unchanged),
+// so a row count with tens of thousands of partials is not bound by one load's latency each.
+static constexpr int SUM_BATCH = 8;
+
+template <bool COHERENT>
 __device__ inline double2 sum_partials2(const double2 *part, int64_t nblk, double2 *sh)
 {
     double2 acc = cmk(0, 0);
-    for (int64_t b = threadIdx.x; b < nblk; b += WG) {
-        const double *pp = (const double *)(part + b);
-        acc = cadd(acc, cmk(load_coherent(pp), load_coherent(pp + 1)));
+    int64_t b = threadIdx.x;
+    if (!COHERENT) {
+        for (; b + (SUM_BATCH - 1) * WG < nblk; b += SUM_BATCH * WG) {
+            double2 v[SUM_BATCH];
+#pragma unroll
+            for (int u = 0; u < SUM_BATCH; ++u) v[u] = part[b + u * WG];
+#pragma unroll
+            for (int u = 0; u < SUM_BATCH; ++u) acc = cadd(acc, v[u]);
+        }
+    }
+    for (; b < nblk; b += WG) {
+        if (COHERENT) {
+            const double *pp = (const double *)(part + b);
+            acc = cadd(acc, cmk(load_coherent(pp), load_coherent(pp + 1)));
+        } else {
+            acc = cadd(acc, part[b]);
+        }
     }
     return block_sum2(acc, sh);
 }
 
+template <bool COHERENT>
 __device__ inline double sum_partials1(const double *part, int64_t nblk, double *sh)
 {
     double acc = 0;
-    for (int64_t b = threadIdx.x; b < nblk; b += WG) acc += load_coherent(part + b);
+    int64_t b = threadIdx.x;
+    if (!COHERENT) {
+        for (; b + (SUM_BATCH - 1) * WG < nblk; b += SUM_BATCH * WG) {
+            double v[SUM_BATCH];
+#pragma unroll
+            for (int u = 0; u < SUM_BATCH; ++u) v[u] = part[b + u * WG];
+#pragma unroll
+            for (int u = 0; u < SUM_BATCH; ++u) acc += v[u];
+        }
+    }
+    for (; b < nblk; b += WG) acc += COHERENT ? load_coherent(part + b) : part[b];
     return block_sum1(acc, sh);
 }
 
@@ -101,10 +136,13 @@ __device__ inline double2 *ring_slot(const SolveDev &s, int slot, const RhsDesc 
     return s.ring + (int64_t)slot * s.ntot + d.voff;
 }
 
-// seed direction buffer (a second parity buffer is kept zeroed and unused)
-__device__ inline double2 *p_buf(const SolveDev &s, const RhsDesc &d, int parity)
+// Seed directions.  With two right-hand sides per SpMV thread (all share one matrix, so
+// voff_j = j n) the pair (2i, 2i+1) is interleaved element by element: one gather of 32 bytes
+// serves both.  Otherwise p_j is the plain vector at voff_j.
+__device__ inline int64_t p_index(const SolveDev &s, int64_t j, const RhsDesc &d, int64_t row)
 {
-    return s.p + (int64_t)parity * s.ntot + d.voff;
+    if (s.spmv_rb == 2) return d.voff - (j & 1) * d.n + 2 * row + (j & 1);
+    return d.voff + row;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -124,8 +162,7 @@ __global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restri
         if (B) b = B[d.voff + row];
         else b = cmk(row == unit_idx[j] ? 1.0 : 0.0, 0.0);
         ring_slot(s, 0, d)[row] = b;
-        p_buf(s, d, 0)[row] = cmk(0, 0);
-        p_buf(s, d, 1)[row] = cmk(0, 0);
+        s.p[p_index(s, j, d, row)] = cmk(0, 0);
     }
     double2 bb = block_sum2(cmul(b, b), sh2);
     double nn = block_sum1(cabs2(b), sh1);
@@ -134,8 +171,8 @@ __global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restri
         s.part1[j * s.nblk + blockIdx.x] = nn;
     }
     if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
-    double2 rho = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
-    double nb = sqrt(sum_partials1(s.part1 + j * s.nblk, gridDim.x, sh1));
+    double2 rho = sum_partials2<true>(s.part2 + j * s.nblk, gridDim.x, sh2);
+    double nb = sqrt(sum_partials1<true>(s.part1 + j * s.nblk, gridDim.x, sh1));
     if (threadIdx.x == 0) {
         SeedState st;
         int sd = seed_idx[j];
@@ -190,16 +227,42 @@ __global__ void __launch_bounds__(WG) k_init_pairs(SolveDev s)
 //   k_rupd    r_{n+1} = r_n - alpha_n q;  partial sums of r.r and |r|^2
 //   k_beta    rho_{n+1}, ||r_{n+1}||, beta_n, convergence of the seed (one workgroup per rhs)
 // ---------------------------------------------------------------------------------------
+// RB right-hand sides per thread: with RB = 2 the interleaved pair (j0, j0+1) is read and
+// written as one 32-byte element.
+template <int RB>
 __global__ void __launch_bounds__(WG) k_pupd(SolveDev s)
 {
-    const int64_t j = blockIdx.y;
-    const SeedState st = s.seed[j];
-    if (!seed_running(st, s.TB)) return;
-    const RhsDesc d = s.desc[j];
+    const int64_t j0 = (int64_t)blockIdx.y * RB;
+    SeedState st[RB];
+    bool run[RB];
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        run[b] = j0 + b < s.K;
+        if (run[b]) {
+            st[b] = s.seed[j0 + b];
+            run[b] = seed_running(st[b], s.TB);
+        }
+        any |= run[b];
+    }
+    if (!any) return;
+    const RhsDesc d = s.desc[j0];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (row >= d.n) return;
-    double2 *p = p_buf(s, d, 0) + row;
-    *p = cfma(st.beta_prev, *p, ring_slot(s, (st.base + st.step) % (s.TB + 1), d)[row]);
+    double2 *p = s.p + p_index(s, j0, d, row);
+    double2 pv[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) pv[b] = p[b];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        if (run[b]) {
+            const double2 r = ring_slot(s, (st[b].base + st[b].step) % (s.TB + 1), s.desc[j0 + b])[row];
+            pv[b] = cfma(st[b].beta_prev, pv[b], r);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+        if (run[b]) p[b] = pv[b];
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by linear index.  With at least 8 groups of
@@ -221,8 +284,22 @@ __device__ inline bool xcd_group_block(int64_t nblk, int64_t G, int64_t &g, int6
     return g < G;
 }
 
+// Matrix arrays reached through a descriptor are global memory; saying so lets the compiler
+// use global (not flat) loads, which wait on the vector-memory counter only.
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T *gptr(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
+// Slots of a slice processed per batch: the column and value loads of SPMV_CHUNK slots are
+// issued together, then their gathers, so each wave has many loads in flight.
+static constexpr int SPMV_CHUNK = 8;
+
 // q = (z_s 1 - H) p for RB right-hand sides that share one matrix (consecutive rhs j0 .. j0+RB-1):
-// the column and value of each slot are loaded once and serve all RB gathers.
+// the column and value of each slot are loaded once and serve all RB gathers.  The products
+// are summed in slot order in every configuration, so a rhs gets the same bits alone or in
+// a batch.
 template <int RB>
 __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
 {
@@ -245,11 +322,12 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
     if (!any) return;
     const RhsDesc d = s.desc[j0];
     const int lane = threadIdx.x & 63;
-    const int64_t slice = rb * 4 + (threadIdx.x >> 6);
+    // one 64-row slice per wave (wave-uniform, so its bookkeeping lives in scalar registers)
+    const int64_t slice = rb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t row = slice * 64 + lane;
-    const double2 *pv[RB];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) pv[b] = s.p + (run[b] ? s.desc[j0 + b].voff : d.voff);
+    // p of rhs j0 + b at row c is pv[RB * c + b] (interleaved pair, or one plain vector); the
+    // gathers of an idle partner (odd K, or a paused seed) read valid memory and are not used
+    const double2 *pv = s.p + p_index(s, j0, d, 0);
     double ax[RB], ay[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
@@ -257,18 +335,40 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
         ay[b] = 0;
     }
     if (slice < d.nslices) {
-        const int64_t off = d.slice_ptr[slice];
-        const int w = d.slice_w[slice];
-        for (int k = 0; k < w; ++k) {
-            const int c = d.ell_col[off + (int64_t)k * 64 + lane];
-            const double v = d.ell_val[off + (int64_t)k * 64 + lane];
+        const int64_t off = gptr(d.slice_ptr)[slice];
+        const int w = gptr(d.slice_w)[slice];
+        const auto *colp = gptr(d.ell_col) + off + lane;
+        const auto *valp = gptr(d.ell_val) + off + lane;
+        int k = 0;
+        for (; k + SPMV_CHUNK <= w; k += SPMV_CHUNK) {
+            int c[SPMV_CHUNK];
+            double v[SPMV_CHUNK];
+#pragma unroll
+            for (int u = 0; u < SPMV_CHUNK; ++u) {
+                c[u] = colp[(int64_t)(k + u) * 64];
+                v[u] = valp[(int64_t)(k + u) * 64];
+            }
+            double2 pc[SPMV_CHUNK][RB];
+#pragma unroll
+            for (int u = 0; u < SPMV_CHUNK; ++u)
+#pragma unroll
+                for (int b = 0; b < RB; ++b) pc[u][b] = pv[(int64_t)RB * c[u] + b];
+#pragma unroll
+            for (int u = 0; u < SPMV_CHUNK; ++u)
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    ax[b] = fma(v[u], pc[u][b].x, ax[b]);
+                    ay[b] = fma(v[u], pc[u][b].y, ay[b]);
+                }
+        }
+        for (; k < w; ++k) {
+            const int c = colp[(int64_t)k * 64];
+            const double v = valp[(int64_t)k * 64];
 #pragma unroll
             for (int b = 0; b < RB; ++b) {
-                if (run[b]) {
-                    const double2 pc = pv[b][c];
-                    ax[b] = fma(v, pc.x, ax[b]);
-                    ay[b] = fma(v, pc.y, ay[b]);
-                }
+                const double2 pc = pv[(int64_t)RB * c + b];
+                ax[b] = fma(v, pc.x, ax[b]);
+                ay[b] = fma(v, pc.y, ay[b]);
             }
         }
     }
@@ -276,7 +376,7 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
     for (int b = 0; b < RB; ++b) {
         double2 pq = cmk(0, 0);
         if (run[b] && slice < d.nslices && row < d.n) {
-            const double2 pr = pv[b][row];
+            const double2 pr = pv[RB * row + b];
             const double2 qv = cfma(st[b].zs, pr, make_double2(-ax[b], -ay[b]));
             s.q[s.desc[j0 + b].voff + row] = qv;
             pq = cmul(pr, qv);
@@ -294,7 +394,7 @@ __global__ void __launch_bounds__(WG) k_alpha(SolveDev s)
     const int64_t j = blockIdx.x;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
-    const double2 tot = sum_partials2(s.part2 + j * s.nblk, s.nblk, sh2);
+    const double2 tot = sum_partials2<false>(s.part2 + j * s.nblk, s.nblk, sh2);
     if (threadIdx.x == 0) {
         if (cis0(tot) || cis0(st.rho)) s.seed[j].status = SEED_BREAKDOWN;
         else s.ahist[j * s.TB + st.step] = cdiv(st.rho, tot);
@@ -338,8 +438,8 @@ __global__ void __launch_bounds__(WG) k_beta(SolveDev s)
     const int64_t j = blockIdx.x;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
-    const double2 rho_new = sum_partials2(s.part2 + j * s.nblk, s.nblk, sh2);
-    const double rnorm = sqrt(sum_partials1(s.part1 + j * s.nblk, s.nblk, sh1));
+    const double2 rho_new = sum_partials2<false>(s.part2 + j * s.nblk, s.nblk, sh2);
+    const double rnorm = sqrt(sum_partials1<false>(s.part1 + j * s.nblk, s.nblk, sh1));
     if (threadIdx.x == 0) {
         const double2 a = s.ahist[j * s.TB + st.step];
         const double2 beta = cdiv(rho_new, st.rho);
@@ -602,14 +702,14 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
             V *up = P + k * d.n + row;
             const V u = cfma(sc, *up, zero);
             *up = u;
-            if (k == st.sw_target) p_buf(s, d, 0)[row] = make_double2((double)u.x, (double)u.y);
+            if (k == st.sw_target) s.p[p_index(s, j, d, row)] = make_double2((double)u.x, (double)u.y);
         }
         rr = cmul(r, r);
     }
     rr = block_sum2(rr, sh2);
     if (threadIdx.x == 0) s.part2[j * s.nblk + blockIdx.x] = rr;
     if (!arrive_last(s.cnt, j, (uint32_t)gridDim.x)) return;
-    const double2 rho = sum_partials2(s.part2 + j * s.nblk, gridDim.x, sh2);
+    const double2 rho = sum_partials2<true>(s.part2 + j * s.nblk, gridDim.x, sh2);
     if (threadIdx.x == 0) {
         s.seed[j].rho = rho;
         s.seed[j].sw_target = -1;
@@ -830,9 +930,10 @@ hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_
 
 hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pupd, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
     const int RB = s.spmv_rb;
     const int64_t G = (s.K + RB - 1) / RB;
+    if (RB == 2) hipLaunchKernelGGL(k_pupd<2>, grid2(s.nblk, G), dim3(WG), 0, st, s);
+    else hipLaunchKernelGGL(k_pupd<1>, grid2(s.nblk, G), dim3(WG), 0, st, s);
     const int64_t nwg = G < 8 ? s.nblk * G : s.nblk * 8 * ((G + 7) / 8);
     if (RB == 2) hipLaunchKernelGGL(k_spmv<2>, dim3((unsigned)nwg), dim3(WG), 0, st, s);
     else hipLaunchKernelGGL(k_spmv<1>, dim3((unsigned)nwg), dim3(WG), 0, st, s);
