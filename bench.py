@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="default fp64 (fp32 storage for the batch workload)")
     ap.add_argument("--problems", type=int, default=8, help="lattices in the batch workload")
+    ap.add_argument("--window", type=int, default=0,
+                    help="G_jj workloads (cubic, batch): shifts per rhs whose full directions are kept "
+                         "(seed candidates); the others cost scalar work only.  0: all")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--shifts-per-wg", type=int, default=0)
     ap.add_argument("--n-rhs", type=int, default=0, help="default 256 (diamond), 32 per lattice (batch)")
@@ -330,7 +333,8 @@ def bench_batch(args, S, torch):
     esz = 8 if prec == "fp32" else 16
     print(f"[bench] workload batch: {len(probs)} lattices L={[p.extra['L'] for p in probs]}, {K} rhs x {M} shifts, "
           f"{prec}; directions {M * ntot * esz / 1e9:.1f} GB", file=sys.stderr, flush=True)
-    opts = dict(tol=tol, max_iter=max_iter, precision=prec, block=args.block, shifts_per_wg=args.shifts_per_wg)
+    opts = dict(tol=tol, max_iter=max_iter, precision=prec, block=args.block, shifts_per_wg=args.shifts_per_wg,
+                window=args.window)
     S.greens_diag_batched(Hs[:1], z[:4], [rhs[0][:1]], fixed_iter=32, precision=prec, block=args.block)
     torch.cuda.synchronize()
     S.set_profiling(True)
@@ -362,7 +366,9 @@ def bench_batch(args, S, torch):
         "dtype": "f64" if prec == "fp64" else "f32-storage/f64-scalars", "data": "synthetic",
         "config": {"workload": (f"{len(probs)} disordered simple-cubic lattices L={Ls} (W in 1,4,8), "
                                 f"{K} unit RHS ({len(rhs[0])} per lattice), {M} shifts eta=0.002, tol {tol:g}, "
-                                f"max_iter {max_iter}, one batched solve"),
+                                f"max_iter {max_iter}, one batched solve"
+                                + (f", full directions for {args.window} seed candidates per rhs" if args.window
+                                   else "")),
                    "n": int(sum(p.H.n for p in probs)), "nnz": int(sum(p.H.nnz for p in probs)), "n_shift": M,
                    "n_rhs": K, "precision": prec, "block": args.block or 24,
                    "iterations_per_step": int(np.max(iters))},
@@ -452,6 +458,10 @@ def main():
         X = torch.empty((K, M, n), dtype=torch.complex128, device=dev)
     opts = dict(tol=p.tol, max_iter=p.max_iter, precision=args.precision, block=args.block,
                 shifts_per_wg=args.shifts_per_wg)
+    if greens:
+        opts["window"] = args.window
+    elif args.window:
+        raise SystemExit("--window applies to the G_jj workloads (cubic, batch)")
 
     def solve():
         if greens:
@@ -505,7 +515,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-storage/f64-scalars",
         "data": "synthetic",
-        "config": {"workload": f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}",
+        "config": {"workload": f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}"
+                               + (f", full directions for {args.window} seed candidates" if args.window else ""),
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
                    "block": args.block or 24, "iterations_per_step": int(np.max(iters))},
         "roofline": update_roofline(upd_ms, upd_bytes, upd_launches, args.workload),

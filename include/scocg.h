@@ -63,7 +63,14 @@ typedef struct {
     int32_t refine;         /* sweeps of FP64 refinement for pairs whose true residual exceeds tol: each solves
                                (z_k - H) d = b - (z_k - H) x per pair (COCG, FP64 vectors) and adds d to x.
                                Needs full solutions (shifted_cocg_solve); implies check_true. */
-    int32_t reserved[4];
+    int32_t window;         /* projection mode only (greens_diag, greens_diag_batched): > 0 keeps the full
+                               direction vector of this many shifts per right-hand side (the seed first, then
+                               the others in the seed-rule order: smallest Im z, Re z nearest Tr(H)/n, lowest
+                               index); every other shift is carried by scalars at the kept row.  A seed switch
+                               then goes to the active stored shift with the largest residual; when none is left
+                               the pairs still active stop unconverged (SCOCG_ENOCONV).  0: every shift keeps
+                               its full direction. */
+    int32_t reserved[3];
 } scocg_opts;
 
 typedef struct {
@@ -119,9 +126,11 @@ int shifted_cocg_solve(scocg_csr_t H, int64_t n_shift, const double *z, int64_t 
  * for the unit right-hand sides e_j, j = rhs_idx[c].
  *   rhs_idx host, n_rhs indices in [0, n)
  *   G       device, [n_shift][n_rhs] complex output
- * Only the diagonal entries of the solutions are kept (the p_k vectors are still
- * full length, which seed switching needs), unless o->keep_tape asks for the
- * full solutions.
+ * Only the diagonal entries of the solutions are kept, unless o->keep_tape asks for
+ * the full solutions.  The directions p_k are kept full length for seed switching,
+ * for every shift or (o->window > 0) for a window of seed candidates; the other
+ * shifts then cost scalar work only (Sec. 3.3: a shifted system needs only scalar
+ * recurrences when one component of its solution is wanted).
  */
 int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,
                 const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream);
@@ -136,8 +145,9 @@ int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, 
  *   G       device, [n_shift][sum n_rhs] complex output (columns in rhs_idx order)
  *   rep     host, [sum n_rhs][n_shift] reports, or NULL
  * Device memory: the directions of every (rhs, shift) pair are stored in full,
- * n_shift * sum_q n_rhs[q] * n_q complex numbers (8 or 16 bytes each); callers
- * split larger batches into waves that fit.
+ * n_shift * sum_q n_rhs[q] * n_q complex numbers (8 or 16 bytes each), or with
+ * o->window > 0 only window * sum_q n_rhs[q] * n_q; callers split larger batches
+ * into waves that fit.
  */
 int greens_diag_batched(int64_t n_problems, const scocg_csr_t *H, const int64_t *n_rhs, const int64_t *rhs_idx,
                         int64_t n_shift, const double *z, const scocg_opts *o, double *G, scocg_pair_report *rep,

@@ -29,7 +29,8 @@ class Opts(ctypes.Structure):
         ("keep_tape", ctypes.c_int32),
         ("no_graph", ctypes.c_int32),
         ("refine", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("window", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -22,7 +22,7 @@ def _require_gpu():
 
 
 def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switching=True, fixed_iter=0, block=0,
-            shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False, refine=0) -> C.Opts:
+            shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False, refine=0, window=0) -> C.Opts:
     o = C.Opts()
     C.load().scocg_default_opts(ctypes.byref(o))
     o.tol = float(tol)
@@ -37,6 +37,7 @@ def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switc
     o.keep_tape = int(bool(keep_tape))
     o.no_graph = int(bool(no_graph))
     o.refine = int(refine)
+    o.window = int(window)
     return o
 
 
@@ -219,7 +220,7 @@ def greens_diag_batched(Hs, z, rhs_lists, allow_noconv=True, allow_breakdown=Fal
 def greens_diag_waves(Hs, z, rhs_lists, max_bytes=64e9, **opts):
     """greens_diag_batched over waves of problems whose stored directions fit in max_bytes."""
     esz = 8 if opts.get("precision", "fp64") in ("fp32", 1) else 16
-    M = len(z)
+    M = len(z) if not opts.get("window") else min(len(z), int(opts["window"]))
     waves, cur, cur_bytes = [], [], 0.0
     for q, (H, r) in enumerate(zip(Hs, rhs_lists)):
         b = esz * M * len(r) * H.n

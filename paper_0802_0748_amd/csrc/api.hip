@@ -364,6 +364,34 @@ int solve(SolveRequest &rq, hipStream_t st)
     const bool fixed = o.fixed_iter > 0;
     const int32_t limit = fixed ? o.fixed_iter : o.max_iter;
     const bool need_full = !rq.projection;
+    if (o.window < 0) return fail(SCOCG_EINVAL, "window must be >= 0");
+    if (o.window > 0 && need_full) return fail(SCOCG_EINVAL, "window needs projection mode (greens_diag without tape)");
+    // window of seed candidates: the only shifts whose full directions are stored
+    const int64_t Mst = (o.window > 0 && o.window < M) ? o.window : M;
+    std::vector<int32_t> h_wshift, h_wslot;
+    if (Mst < M) {
+        h_wshift.resize((size_t)K * Mst);
+        h_wslot.assign((size_t)K * M, -1);
+        std::vector<int32_t> order(M);
+        for (int64_t j = 0; j < K; ++j) {
+            // the seed first, then the seed rule's order: smallest Im z, Re z nearest Tr(H)/n, index
+            for (int64_t k = 0; k < M; ++k) order[k] = (int32_t)k;
+            const double c = centre[j];
+            const int32_t sd = seeds[j];
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                if ((a == sd) != (b == sd)) return a == sd;
+                const double ia = rq.z[2 * a + 1], ib = rq.z[2 * b + 1];
+                if (ia != ib) return ia < ib;
+                const double da = std::fabs(rq.z[2 * a] - c), db = std::fabs(rq.z[2 * b] - c);
+                if (da != db) return da < db;
+                return a < b;
+            });
+            for (int64_t w = 0; w < Mst; ++w) {
+                h_wshift[j * Mst + w] = order[w];
+                h_wslot[j * M + order[w]] = (int32_t)w;
+            }
+        }
+    }
     const size_t KM = (size_t)K * M;
     const size_t vec = (size_t)ntot;
     const size_t esz = o.precision == 0 ? sizeof(double2) : sizeof(float2);
@@ -395,10 +423,14 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.nblk = (n + 255) / 256;
     s.shifts_per_wg = G;
     s.zper = rq.zper ? 1 : 0;
-    s.spmv_rb = (uniform && K >= 2) ? 2 : 1;
+    // two right-hand sides per SpMV thread when every pair (2i, 2i+1) shares its matrix (their
+    // vectors are then adjacent, which the interleaved direction layout needs)
+    bool pairable = K >= 2;
+    for (int64_t j = 0; j + 1 < K && pairable && !rq.Hj.empty(); j += 2) pairable = rq.Hj[j] == rq.Hj[j + 1];
+    s.spmv_rb = pairable ? 2 : 1;
 
     DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
-        brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc;
+        brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc, bwshift, bwslot, bUproj;
     auto A = [&](DevBuf &b, size_t bytes) -> hipError_t { return b.alloc(bytes); };
     hipError_t e = hipSuccess;
 #define ALLOC(buf, bytes)                                                                                  \
@@ -413,7 +445,12 @@ int solve(SolveRequest &rq, hipStream_t st)
     ALLOC(bring, (size_t)(TB + 1) * vec * sizeof(double2));
     ALLOC(bp, 2 * vec * sizeof(double2));
     ALLOC(bq, vec * sizeof(double2));
-    ALLOC(bP, (size_t)M * ntot * esz);
+    ALLOC(bP, (size_t)Mst * ntot * esz);
+    if (Mst < M) {
+        ALLOC(bwshift, (size_t)K * Mst * sizeof(int32_t));
+        ALLOC(bwslot, KM * sizeof(int32_t));
+        ALLOC(bUproj, KM * sizeof(double2));
+    }
     const bool x_is_out = need_full && o.precision == 0 && rq.Xout && !rq.keepX;
     if (need_full && !x_is_out) ALLOC(bX, (size_t)M * ntot * esz);
     ALLOC(bdesc, K * sizeof(RhsDesc));
@@ -446,6 +483,10 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.p = bp.as<double2>();
     s.q = bq.as<double2>();
     s.P = bP.ptr;
+    s.Mst = Mst;
+    s.wshift = Mst < M ? bwshift.as<int32_t>() : nullptr;
+    s.wslot = Mst < M ? bwslot.as<int32_t>() : nullptr;
+    s.Uproj = Mst < M ? bUproj.as<double2>() : nullptr;
     s.X = need_full ? (x_is_out ? (void *)rq.Xout : bX.ptr) : nullptr;
     s.Xproj = need_full ? nullptr : bXproj.as<double2>();
     s.proj_row = need_full ? nullptr : bprow.as<int64_t>();
@@ -468,6 +509,11 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.desc = bdesc.as<RhsDesc>();
 
     HIPCHK(hipMemcpyAsync(bdesc.ptr, hdesc.data(), K * sizeof(RhsDesc), hipMemcpyHostToDevice, st));
+    if (Mst < M) {
+        HIPCHK(hipMemcpyAsync(bwshift.ptr, h_wshift.data(), h_wshift.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              st));
+        HIPCHK(hipMemcpyAsync(bwslot.ptr, h_wslot.data(), h_wslot.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    }
     HIPCHK(hipMemcpyAsync(bz.ptr, rq.z, nz * sizeof(double2), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bsd.ptr, seeds.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
     if (rq.unit_idx) {

@@ -39,20 +39,16 @@ __device__ inline void st_nt(float2 *p, float2 v)
     __builtin_nontemporal_store(w, (f2v *)p);
 }
 
-// Projection mode: TB steps for the NP pairs k .. k+NP-1 (of those below k1) held in
-// registers, with or without the x_k update; pair p's (a', b') table starts at
-// coef + p * TB * 2.
+// Projection mode: TB steps for NP pairs held in registers, with or without the x_k update;
+// pair cp[q]'s (a', b') table starts at coef + cp[q] * TB * 2.
 template <int TB, typename V, int NP, bool WITH_X>
-__device__ inline void apply_steps(const V *coef, int64_t pair0, int64_t k, int64_t k1, const V (&r)[TB],
-                                   V (&x)[NP], V (&u)[NP])
+__device__ inline void apply_steps(const V *coef, const int64_t (&cp)[NP], const V (&r)[TB], V (&x)[NP], V (&u)[NP])
 {
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            // a slot past the group's end reuses the first pair's table (its result is not stored)
-            const int64_t kq = (k + q < k1) ? k + q : k;
-            const V *cf = coef + ((pair0 + kq) * TB + t) * 2;
+            const V *cf = coef + (cp[q] * TB + t) * 2;
             u[q] = cfma(cf[1], u[q], r[t]);
             if (WITH_X) x[q] = cfma(cf[0], u[q], x[q]);
         }
@@ -65,7 +61,7 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
                                               V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
                                               const int64_t *__restrict__ proj_row,
                                               const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
-                                              int ngroups)
+                                              int ngroups, const int32_t *__restrict__ wshift, int64_t Mst)
 {
     // Row blocks run fastest in dispatch order, so the concurrently running workgroups of one
     // shift group stream long contiguous stretches of each pair's x and u.  (Dealing the shift
@@ -82,11 +78,14 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     const int64_t voff = desc[j].voff;
     const int64_t row = rb * WG + threadIdx.x;
     if (row >= n) return;
+    // stored-direction slots k0 .. k1-1 of this workgroup; slot w holds shift kof(w) (a window
+    // of seed candidates in projection mode, else shift w)
     const int64_t k0 = (int64_t)g * G;
-    const int64_t k1 = min(k0 + G, M);
+    const int64_t k1 = min(k0 + G, Mst);
+    auto kof = [&](int64_t w) -> int64_t { return (PROJ && wshift) ? (int64_t)wshift[j * Mst + w] : w; };
     // late in a solve most shift groups are frozen: skip them before reading the history
     bool group_active = false;
-    for (int64_t k = k0; k < k1; ++k) group_active = group_active || nact[j * M + k] > 0;
+    for (int64_t k = k0; k < k1; ++k) group_active = group_active || nact[j * M + kof(k)] > 0;
     if (!group_active) return;
     V r[TB];
 #pragma unroll
@@ -95,7 +94,7 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
         else r[t] = to_v<V>(cmk(0, 0));
     }
     X += M * voff;
-    P += M * voff;
+    P += Mst * voff;
     const int64_t prow = PROJ ? proj_row[j] : -1;
     // projection mode needs x_k only in the workgroup that holds the kept row (uniform test)
     const int64_t row0 = rb * WG;
@@ -106,7 +105,7 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
         bool any = false;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int64_t pair = j * M + k + q;
+            const int64_t pair = j * M + kof(k + q < k1 ? k + q : k);
             na[q] = (k + q < k1) ? nact[pair] : 0;
             any = any || na[q] > 0;
             x[q] = to_v<V>(cmk(0, 0));
@@ -136,12 +135,16 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
                 }
             }
         } else {
-            if (with_x) apply_steps<TB, V, NP, true>(coef, j * M, k, k1, r, x, u);
-            else apply_steps<TB, V, NP, false>(coef, j * M, k, k1, r, x, u);
+            // a slot past the group's end reuses the first pair's table (its result is not stored)
+            int64_t cp[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) cp[q] = j * M + kof(k + q < k1 ? k + q : k);
+            if (with_x) apply_steps<TB, V, NP, true>(coef, cp, r, x, u);
+            else apply_steps<TB, V, NP, false>(coef, cp, r, x, u);
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int64_t pair = j * M + k + q;
+            const int64_t pair = j * M + kof(k + q < k1 ? k + q : k);
             if (na[q] > 0) {
                 st_nt(P + (k + q) * n + row, u[q]);
                 if (PROJ) {
@@ -158,16 +161,17 @@ template <int TB, typename V, int NP>
 static hipError_t flush_v(const SolveDev &s, hipStream_t st)
 {
     const int G = s.shifts_per_wg;
-    const int ng = (int)((s.M + G - 1) / G);
+    const int ng = (int)((s.Mst + G - 1) / G);
     if (s.K * ng > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const dim3 g((unsigned)s.nblk, (unsigned)(s.K * ng));
     const V *coef = (const V *)s.coef;
     if (s.Xproj)
         hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)nullptr,
-                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng);
+                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst);
     else
         hipLaunchKernelGGL((k_flush<TB, V, NP, false>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)s.X,
-                           (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng);
+                           (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng,
+                           (const int32_t *)nullptr, s.M);
     return hipGetLastError();
 }
 

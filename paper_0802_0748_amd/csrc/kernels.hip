@@ -74,9 +74,9 @@ __device__ inline bool arrive_last(uint32_t *cnt, int64_t j, uint32_t nblk)
 // as a tree.  COHERENT: the partials were written by other workgroups of the same launch
 // (read past the caches with atomic loads); otherwise by an earlier launch (plain loads, which
 // the compiler can issue many at a time).
-// With plain loads a thread fetches 8 of its partials at a time (the sum order is unchanged),
+// With plain loads a thread fetches 32 of its partials at a time (the sum order is unchanged),
 // so a row count with tens of thousands of partials is not bound by one load's latency each.
-static constexpr int SUM_BATCH = 8;
+static constexpr int SUM_BATCH = 32;
 
 template <bool COHERENT>
 __device__ inline double2 sum_partials2(const double2 *part, int64_t nblk, double2 *sh)
@@ -136,9 +136,9 @@ __device__ inline double2 *ring_slot(const SolveDev &s, int slot, const RhsDesc 
     return s.ring + (int64_t)slot * s.ntot + d.voff;
 }
 
-// Seed directions.  With two right-hand sides per SpMV thread (all share one matrix, so
-// voff_j = j n) the pair (2i, 2i+1) is interleaved element by element: one gather of 32 bytes
-// serves both.  Otherwise p_j is the plain vector at voff_j.
+// Seed directions.  With two right-hand sides per SpMV thread (rhs 2i and 2i+1 share one
+// matrix, so voff_{2i+1} = voff_{2i} + n) the pair is interleaved element by element from
+// voff_{2i} on: one gather of 32 bytes serves both.  Otherwise p_j is the plain vector at voff_j.
 __device__ inline int64_t p_index(const SolveDev &s, int64_t j, const RhsDesc &d, int64_t row)
 {
     if (s.spmv_rb == 2) return d.voff - (j & 1) * d.n + 2 * row + (j & 1);
@@ -216,6 +216,7 @@ __global__ void __launch_bounds__(WG) k_init_pairs(SolveDev s)
     s.active[pair] = live ? 1 : 0;
     s.nact[pair] = 0;
     if (s.Xproj) s.Xproj[pair] = cmk(0, 0);
+    if (s.Uproj) s.Uproj[pair] = cmk(0, 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -524,6 +525,20 @@ __device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t
     s.active[pair] = act;
     s.nact[pair] = na;
     if (na == 0) return 0ull;
+    if (s.wslot && s.wslot[pair] < 0) {
+        // no stored direction: carry x_k and u_k at the kept row only, with the same
+        // arithmetic the deferred update applies to a stored direction
+        const int64_t at = s.desc[j].voff + s.proj_row[j];
+        V x = to_v<V>(s.Xproj[pair]), u = to_v<V>(s.Uproj[pair]);
+        for (int t = 0; t < na; ++t) {
+            const V r = to_v<V>(s.ring[(int64_t)((st.base + t) % (s.TB + 1)) * s.ntot + at]);
+            u = cfma(cf[2 * t + 1], u, r);
+            x = cfma(cf[2 * t + 0], u, x);
+        }
+        s.Xproj[pair] = make_double2((double)x.x, (double)x.y);
+        s.Uproj[pair] = make_double2((double)u.x, (double)u.y);
+        return 0ull;
+    }
     // Steps past the pair's last one are padded with a' = 0, b' = 1, which leaves x_k
     // unchanged (and u_k too while the residual history is zero there), so the deferred
     // update runs every step without a per-pair branch.
@@ -585,7 +600,8 @@ __global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
         if (s.active[pair]) {
             cnt++;
             const double r = s.res[pair];
-            if (r > br) {
+            // a switch needs the new seed's full direction
+            if (r > br && (!s.wslot || s.wslot[pair] >= 0)) {
                 br = r;
                 bi = (int)k;
             }
@@ -624,6 +640,13 @@ __global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
         } else if (st.status == SEED_PAUSED) {
             sw = sh_idx[0];
             w.status = SEED_RUNNING;
+            if (sw < 0) {
+                // no stored direction is left to switch to: iterating the converged seed further
+                // would let rounding break the collinearity of the residuals, so the pairs still
+                // active stop here, unconverged
+                w.status = SEED_STOPPED;
+                mb = 2;
+            }
         } else if (st.status == SEED_LIMIT) {
             w.status = SEED_STOPPED;
         }
@@ -642,10 +665,11 @@ __global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
     }
     __syncthreads();
     if (dec_brk) {
+        // 1: breakdown ends every active pair; 2: they stop unconverged (status stays NOCONV)
         for (int64_t k = tid; k < s.M; k += WG) {
             const int64_t pair = j * s.M + k;
             if (s.active[pair]) {
-                s.pstatus[pair] = PAIR_BREAKDOWN;
+                if (dec_brk == 1) s.pstatus[pair] = PAIR_BREAKDOWN;
                 s.active[pair] = 0;
             }
         }
@@ -694,17 +718,29 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
         double2 *rp = ring_slot(s, st.base, d) + row;
         const double2 r = cmul(*rp, st.inv_pt);
         *rp = r;
-        V *P = (V *)s.P + s.M * d.voff;
+        V *P = (V *)s.P + s.Mst * d.voff;
         const V sc = to_v<V>(st.inv_ppt);
         const V zero = to_v<V>(cmk(0, 0));
-        for (int64_t k = 0; k < s.M; ++k) {
+        for (int64_t w = 0; w < s.Mst; ++w) {
+            const int64_t k = s.wshift ? s.wshift[j * s.Mst + w] : w;
             if (!s.active[j * s.M + k]) continue;
-            V *up = P + k * d.n + row;
+            V *up = P + w * d.n + row;
             const V u = cfma(sc, *up, zero);
             *up = u;
             if (k == st.sw_target) s.p[p_index(s, j, d, row)] = make_double2((double)u.x, (double)u.y);
         }
         rr = cmul(r, r);
+    }
+    if (s.wslot && blockIdx.x == 0) {
+        // the same rescale for the pairs carried by scalars at the kept row
+        const V sc = to_v<V>(st.inv_ppt);
+        const V zero = to_v<V>(cmk(0, 0));
+        for (int64_t k = threadIdx.x; k < s.M; k += WG) {
+            const int64_t pair = j * s.M + k;
+            if (!s.active[pair] || s.wslot[pair] >= 0) continue;
+            const V u = cfma(sc, to_v<V>(s.Uproj[pair]), zero);
+            s.Uproj[pair] = make_double2((double)u.x, (double)u.y);
+        }
     }
     rr = block_sum2(rr, sh2);
     if (threadIdx.x == 0) s.part2[j * s.nblk + blockIdx.x] = rr;

@@ -114,8 +114,12 @@ struct SolveDev {
     SeedState *seed;           // [K]
     double2 *ring;             // [(TB+1)][K][n]
     double2 *p, *q;            // [K][n]
-    void *X, *P;               // [K][M][n] (double2 or float2); X may be null in projection mode.
-                               // P holds the scaled directions u_k = pi_k p_k (see k_flush)
+    void *X, *P;               // X [K][M][n], P [K][Mst][n] (double2 or float2); X is null in projection
+                               // mode.  P holds the scaled directions u_k = pi_k p_k (see k_flush)
+    int64_t Mst;               // direction vectors stored per rhs: M, or the window of seed candidates
+    const int32_t *wshift;     // [K][Mst] shift of each stored direction, or null (slot w is shift w)
+    const int32_t *wslot;      // [K*M] stored-direction slot of each pair or -1, or null (identity)
+    double2 *Uproj;            // [K*M] u_k at the kept row for pairs without a stored direction, or null
     double2 *Xproj;            // [K][M] projected solution (projection mode) or null
     const int64_t *proj_row;   // [K] row kept in projection mode
     double2 *pi, *pi_prev, *beta_k; // [K*M]
@@ -130,7 +134,7 @@ struct SolveDev {
     int64_t nblk;              // row blocks of 256
     int shifts_per_wg;
     int zper;                  // 1: one shift per rhs (M = 1, z has K entries), used by refinement
-    int spmv_rb;               // right-hand sides per SpMV thread (2 needs one shared matrix)
+    int spmv_rb;               // right-hand sides per SpMV thread (2: each rhs pair 2i, 2i+1 shares its matrix)
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
 };
 

@@ -285,6 +285,88 @@ def test_batched_uneven_hamiltonians_equal_separate_solves():
             assert np.max(np.abs(g - ref["X"][:, j]) * z.imag) < 2 * 20 * 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_window_fixed_iterations_equal_full_directions(precision):
+    """Window of seed candidates (projection mode): the shifts carried by scalars at the kept
+    row get the same arithmetic as the stored directions, so without freezing or switching
+    G is bit for bit the full-direction result."""
+    S = _S()
+    rng = np.random.default_rng(21)
+    L = 9
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    H = S.Hamiltonian.from_csr(Hc)
+    z = np.linspace(-6, 6, 13) + 1j * np.linspace(0.05, 0.3, 13)
+    rhs = [0, 17, 400]
+    G0, _, _, _ = S.greens_diag(H, z, rhs, fixed_iter=61, precision=precision)
+    for w in (1, 3, 12):
+        Gw, _, _, _ = S.greens_diag(H, z, rhs, fixed_iter=61, precision=precision, window=w)
+        assert np.array_equal(Gw.cpu().numpy(), G0.cpu().numpy()), w
+
+
+@pytest.mark.parametrize("window", [1, 2, 4])
+def test_window_production_matches_oracle(window):
+    """Tolerance-stopped greens_diag with a window of seed candidates.  The seed switches to
+    the stored shift with the largest residual; every converged G_jj(z_k) agrees with the
+    oracle within the residual bounds of Sec. 3.4.  With window 1 (only the fast seed stored)
+    nothing is left to switch to when the seed converges: the other pairs stop unconverged."""
+    S = _S()
+    rng = np.random.default_rng(22)
+    L = 8
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    H = S.Hamiltonian.from_csr(Hc)
+    # the seed (shift 0, the largest Im z) converges first, so switching is exercised
+    z = np.linspace(-6.5, 6.5, 12) + 1j * np.concatenate([[0.5], np.full(11, 0.04)])
+    rhs = np.array([0, 5, 300])
+    tol = 1e-10
+    G, rep, _, rc = S.greens_diag(H, z, rhs, tol=tol, max_iter=6000, window=window, seed_index=0)
+    sw = S.last_timing()["switches"]
+    if window == 1:
+        assert rc == 5 and sw == 0
+        assert np.all(rep["status"][:, 0] == 0) and np.any(rep["status"][:, 1:] == 5)
+    else:
+        assert rc == 0 and np.all(rep["status"] == 0) and sw > 0
+    G = G.cpu().numpy()
+    for c, j in enumerate(rhs):
+        ref = O.shifted_cocg(Hc, z, O.unit(Hc.n, int(j)), tol=tol, max_iter=6000)
+        assert np.all(ref["status"] == 0)
+        ok = rep["status"][c] == 0
+        err = np.abs(G[ok, c] - ref["X"][ok, j]) * z.imag[ok]
+        assert np.max(err) < 2 * 20 * tol, (window, c, np.max(err))
+
+
+def test_window_batched_uneven_matches_full_batched():
+    """Batched uneven lattices with a window: every pair the window lets converge is within
+    the residual bounds of the full-direction batched solve; pairs left without a stored
+    switch candidate are reported unconverged, never wrong."""
+    S = _S()
+    rng = np.random.default_rng(23)
+    Ls = [6, 9, 7]
+    Hcs = [simple_cubic(L, rng.uniform(-2, 2, L ** 3)) for L in Ls]
+    Hs = [S.Hamiltonian.from_csr(h) for h in Hcs]
+    rhs = [np.sort(rng.choice(h.n, size=4, replace=False)) for h in Hcs]
+    z = np.linspace(-6, 6, 16) + 0.05j
+    tol = 1e-10
+    Gf, repf, rcf = S.greens_diag_batched(Hs, z, rhs, tol=tol, max_iter=6000)
+    Gw, repw, rcw = S.greens_diag_batched(Hs, z, rhs, tol=tol, max_iter=6000, window=3)
+    assert rcf == 0 and rcw in (0, 5)
+    n_ok = 0
+    for q in range(len(Ls)):
+        ok = (repw[q]["status"] == 0).T  # [n_shift][n_rhs] like G
+        n_ok += int(ok.sum())
+        err = np.abs(Gw[q].cpu().numpy() - Gf[q].cpu().numpy()) * z.imag[:, None]
+        assert np.max(err[ok]) < 2 * 20 * tol
+        assert np.all(repw[q]["status"][repw[q]["status"] != 0] == 5)
+    assert n_ok >= 0.5 * len(z) * sum(len(r) for r in rhs)
+
+
+def test_window_needs_projection_mode():
+    S = _S()
+    Hc, z, B = _problem(50, 3)
+    H = S.Hamiltonian.from_csr(Hc)
+    with pytest.raises(RuntimeError):
+        S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), window=2)
+
+
 def test_zero_rhs_and_breakdown():
     S = _S()
     rng = np.random.default_rng(0)
