@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="default fp64 (fp32 storage for the batch workload)")
     ap.add_argument("--problems", type=int, default=8, help="lattices in the batch workload")
+    ap.add_argument("--matrix-free", action="store_true",
+                    help="hubbard workload: apply H from per-species hopping tables (hubbard_upload)")
     ap.add_argument("--window", type=int, default=0,
                     help="G_jj workloads (cubic, batch): shifts per rhs whose full directions are kept "
                          "(seed candidates); the others cost scalar work only.  0: all")
@@ -450,7 +452,14 @@ def main():
         return 0
     args.precision = args.precision or "fp64"
     p, desc = load_workload(args)
-    H = S.Hamiltonian.from_csr(p.H)
+    if args.matrix_free:
+        if args.workload != "hubbard":
+            raise SystemExit("--matrix-free applies to the hubbard workload")
+        e = p.extra
+        H = S.Hamiltonian.hubbard(e["L"], e["n_up"], e["n_dn"], t=1.0, U=4.0, V=1.0)
+        desc += ", matrix-free operator"
+    else:
+        H = S.Hamiltonian.from_csr(p.H)
     K, M, n = p.n_rhs, len(p.z), p.H.n
     greens = args.workload == "cubic"
     if not greens:

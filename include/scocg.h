@@ -104,6 +104,24 @@ int csr_upload(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t *co
 int csr_update_values(scocg_csr_t H, const double *val, void *stream);
 
 /* Dimension and stored-entry count of an uploaded matrix. */
+/*
+ * Matrix-free extended Hubbard ring (the model class of Sec. 4.2: a many-electron
+ * Hamiltonian in the occupation-number basis of one (N_up, N_dn) sector):
+ *     H = -t sum_{i,s} (c+_{i,s} c_{i+1,s} + h.c.) + U sum_i n_{i,up} n_{i,dn} + V sum_i n_i n_{i+1}
+ * on L sites with periodic boundary.  Basis: each species is an L-bit occupation pattern
+ * with N_s bits set, in increasing order; row = i_up * D_dn + i_dn.  Fermion signs follow
+ * the Jordan-Wigner order with all up-spin modes before all down-spin modes (the
+ * ring-closing hop carries (-1)^(N_s - 1)).  The operator applies H = T_up (x) 1 + 1 (x) T_dn
+ * + D from two hopping tables of D_up and D_dn configurations instead of storing the
+ * matrix; its products equal those of the stored matrix of the same sector bit for bit.
+ *   3 <= L <= 30, 0 <= n_up, n_dn <= L, D_up * D_dn < 2^31; t, U, V finite.
+ * The handle works with shifted_cocg_solve, greens_diag and greens_diag_batched;
+ * csr_update_values, density_matrix_energy and backward need a stored matrix (EINVAL).
+ * csr_nnz reports the entries the stored matrix would have.  Free with csr_free.
+ */
+int hubbard_upload(int32_t L, int32_t n_up, int32_t n_dn, double t, double U, double V, void *stream,
+                   scocg_csr_t *out);
+
 int64_t csr_n(scocg_csr_t H);
 int64_t csr_nnz(scocg_csr_t H);
 void csr_free(scocg_csr_t H);

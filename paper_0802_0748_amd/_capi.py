@@ -59,6 +59,7 @@ EXPORTED = [
     "scocg_default_opts",
     "scocg_csr_validate",
     "csr_upload",
+    "hubbard_upload",
     "csr_update_values",
     "csr_n",
     "csr_nnz",
@@ -95,6 +96,9 @@ def load():
     lib.scocg_csr_validate.restype = i32
     lib.csr_upload.argtypes = [i64, i64, P, P, P, i32, P, ctypes.POINTER(P)]
     lib.csr_upload.restype = i32
+    lib.hubbard_upload.argtypes = [i32, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, P,
+                                   ctypes.POINTER(P)]
+    lib.hubbard_upload.restype = i32
     lib.csr_update_values.argtypes = [P, P, P]
     lib.csr_update_values.restype = i32
     lib.csr_n.argtypes = [P]

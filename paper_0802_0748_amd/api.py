@@ -71,6 +71,22 @@ class Hamiltonian:
     def from_csr(cls, H, validate=True):
         return cls(H.row_ptr, H.col, H.val, validate=validate)
 
+    @classmethod
+    def hubbard(cls, L, n_up, n_dn, t=1.0, U=4.0, V=1.0):
+        """Matrix-free extended Hubbard ring (hubbard_upload): the sector Hamiltonian applied
+        from per-species hopping tables instead of a stored matrix."""
+        _require_gpu()
+        lib = C.load()
+        self = cls.__new__(cls)
+        h = ctypes.c_void_p()
+        C.check(lib.hubbard_upload(int(L), int(n_up), int(n_dn), float(t), float(U), float(V), _stream_ptr(),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.n = int(lib.csr_n(h))
+        self.nnz = int(lib.csr_nnz(h))
+        self.row_ptr = self.col = None
+        return self
+
     @property
     def handle(self):
         return self._h

@@ -130,7 +130,8 @@ extern "C" int scocg_csr_validate(int64_t n, int64_t nnz, const int64_t *rp, con
 
 static void free_dev(DevCSR &d)
 {
-    void *ptrs[] = {d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.d_ell_pos, d.d_row_ptr, d.d_col, d.d_val};
+    void *ptrs[] = {d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.d_ell_pos, d.d_row_ptr, d.d_col, d.d_val,
+                    d.d_hub, d.d_hub_tables};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     std::memset(&d, 0, sizeof(d));
@@ -223,10 +224,145 @@ extern "C" int csr_upload(int64_t n, int64_t nnz, const int64_t *rp, const int64
     return SCOCG_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// matrix-free extended Hubbard ring
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// One spin species on an L-site ring with n electrons: configurations (L-bit patterns with n
+// bits set, ascending) and the hopping lists -t sum_i (c+_i c_i+1 + h.c.).  Signs follow the
+// Jordan-Wigner order with all up-spin modes before all down-spin modes: a hop between
+// neighbours i, i+1 passes no electron of its species, the ring-closing hop (L-1, 0) passes
+// the other n - 1.  A hop entry is the target index, with bit 31 set when its value is +t.
+struct Species {
+    std::vector<uint32_t> conf;
+    std::vector<int32_t> ptr;
+    std::vector<uint32_t> hop;
+};
+
+Species build_species(int L, int n)
+{
+    Species sp;
+    if (n == 0) {
+        sp.conf.push_back(0);
+    } else {
+        // next L-bit pattern with the same number of bits set, in increasing order
+        uint64_t c = (1ull << n) - 1;
+        while (c < (1ull << L)) {
+            sp.conf.push_back((uint32_t)c);
+            const uint64_t lo = c & (~c + 1);
+            const uint64_t r = c + lo;
+            c = (((r ^ c) >> 2) / lo) | r;
+        }
+    }
+    sp.ptr.push_back(0);
+    std::vector<uint32_t> row;
+    for (uint32_t c : sp.conf) {
+        row.clear();
+        for (int i = 0; i < L; ++i) {
+            const int j = (i + 1) % L;
+            if (((c >> i) & 1u) == ((c >> j) & 1u)) continue;
+            const uint32_t nc = c ^ ((1u << i) | (1u << j));
+            const int sign = (i == L - 1 && (n - 1) % 2 != 0) ? -1 : 1;
+            const uint32_t k = (uint32_t)(std::lower_bound(sp.conf.begin(), sp.conf.end(), nc) - sp.conf.begin());
+            // value -t * sign: +t exactly when sign = -1
+            row.push_back(k | (sign < 0 ? 0x80000000u : 0u));
+        }
+        std::sort(row.begin(), row.end(), [](uint32_t a, uint32_t b) { return (a & 0x7fffffffu) < (b & 0x7fffffffu); });
+        sp.hop.insert(sp.hop.end(), row.begin(), row.end());
+        sp.ptr.push_back((int32_t)sp.hop.size());
+    }
+    return sp;
+}
+
+int popc32(uint32_t x) { return __builtin_popcount(x); }
+
+}  // namespace
+
+extern "C" int hubbard_upload(int32_t L, int32_t n_up, int32_t n_dn, double t, double U, double V, void *stream,
+                              scocg_csr_t *out)
+{
+    g_err.clear();
+    if (!out) return fail(SCOCG_EINVAL, "out is null");
+    *out = nullptr;
+    if (L < 3 || L > 30) return fail(SCOCG_EINVAL, "ring length must be in [3, 30]");
+    if (n_up < 0 || n_up > L || n_dn < 0 || n_dn > L) return fail(SCOCG_EINVAL, "electron counts must be in [0, L]");
+    if (!std::isfinite(t) || !std::isfinite(U) || !std::isfinite(V)) return fail(SCOCG_EINVAL, "non-finite parameter");
+    const Species up = build_species(L, n_up), dn = build_species(L, n_dn);
+    const int64_t Du = (int64_t)up.conf.size(), Dd = (int64_t)dn.conf.size();
+    const int64_t n = Du * Dd;
+    if (n >= (1LL << 31)) return fail(SCOCG_EINVAL, "sector dimension must be below 2^31");
+    hipStream_t st = (hipStream_t)stream;
+    scocg_csr *H = new scocg_csr();
+    DevCSR &d = H->d;
+    d.n = n;
+    d.nnz = Dd * (int64_t)up.hop.size() + Du * (int64_t)dn.hop.size() + n;  // entries of the stored matrix
+    d.nslices = (n + 63) / 64;
+    int maxw = 0;
+    for (int64_t a = 0; a < Du; ++a)
+        for (int64_t b = 0; b < Dd; ++b)
+            maxw = std::max<int>(maxw, up.ptr[a + 1] - up.ptr[a] + dn.ptr[b + 1] - dn.ptr[b] + 1);
+    d.max_w = maxw;
+    // trace in row order, as a sum over the stored diagonal would give
+    double tr = 0;
+    for (int64_t a = 0; a < Du; ++a) {
+        const uint32_t cu = up.conf[a];
+        for (int64_t b = 0; b < Dd; ++b) {
+            const uint32_t cd = dn.conf[b];
+            auto nxt = [&](uint32_t c) { return ((c >> 1) | ((c & 1u) << (L - 1))) & ((1u << L) - 1u); };
+            const int on = popc32(cu & cd);
+            const int inter = popc32(cu & nxt(cu)) + popc32(cd & nxt(cd)) + popc32(cu & nxt(cd)) + popc32(cd & nxt(cu));
+            tr += U * (double)on + V * (double)inter;
+        }
+    }
+    d.trace = tr;
+    // one device block: up ptr, hop, conf, then the same for down
+    auto bytes4 = [](size_t c) { return ((c * 4 + 255) / 256) * 256; };
+    const size_t o_uptr = 0, o_uhop = o_uptr + bytes4(up.ptr.size()), o_ucf = o_uhop + bytes4(up.hop.size());
+    const size_t o_dptr = o_ucf + bytes4(up.conf.size()), o_dhop = o_dptr + bytes4(dn.ptr.size());
+    const size_t o_dcf = o_dhop + bytes4(dn.hop.size()), total = o_dcf + bytes4(dn.conf.size());
+    std::vector<char> blob(total, 0);
+    std::memcpy(blob.data() + o_uptr, up.ptr.data(), up.ptr.size() * 4);
+    std::memcpy(blob.data() + o_uhop, up.hop.data(), up.hop.size() * 4);
+    std::memcpy(blob.data() + o_ucf, up.conf.data(), up.conf.size() * 4);
+    std::memcpy(blob.data() + o_dptr, dn.ptr.data(), dn.ptr.size() * 4);
+    std::memcpy(blob.data() + o_dhop, dn.hop.data(), dn.hop.size() * 4);
+    std::memcpy(blob.data() + o_dcf, dn.conf.data(), dn.conf.size() * 4);
+    char *dev = nullptr;
+    hipError_t e = upload(&dev, blob.data(), blob.size(), st);
+    d.d_hub_tables = dev;
+    HubbardOp h{};
+    if (e == hipSuccess) {
+        h.up_ptr = (const int32_t *)(dev + o_uptr);
+        h.up_hop = (const uint32_t *)(dev + o_uhop);
+        h.up_conf = (const uint32_t *)(dev + o_ucf);
+        h.dn_ptr = (const int32_t *)(dev + o_dptr);
+        h.dn_hop = (const uint32_t *)(dev + o_dhop);
+        h.dn_conf = (const uint32_t *)(dev + o_dcf);
+        h.Dd = Dd;
+        h.t = t;
+        h.U = U;
+        h.V = V;
+        h.L = L;
+        e = upload(&d.d_hub, &h, 1, st);
+    }
+    if (e != hipSuccess) {
+        free_dev(d);
+        delete H;
+        return fail(e == hipErrorOutOfMemory ? SCOCG_ENOMEM : SCOCG_EHIP, std::string("hubbard_upload: ") +
+                                                                              hipGetErrorString(e));
+    }
+    *out = H;
+    return SCOCG_OK;
+}
+
+static bool matrix_free(const scocg_csr *H) { return H && H->d.d_hub; }
+
 extern "C" int csr_update_values(scocg_csr_t H, const double *val, void *stream)
 {
     g_err.clear();
     if (!H || !val) return fail(SCOCG_EINVAL, "null argument");
+    if (matrix_free(H)) return fail(SCOCG_EINVAL, "a matrix-free operator has no stored values");
     hipStream_t st = (hipStream_t)stream;
     DevCSR &d = H->d;
     std::vector<double> eval(d.ell_nnz, 0.0);
@@ -326,7 +462,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     bool uniform = true;
     for (int64_t j = 0; j < K; ++j) {
         const DevCSR &d = (rq.Hj.empty() ? rq.H : rq.Hj[j])->d;
-        hdesc[j] = RhsDesc{d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.nslices, d.n, ntot, 0};
+        hdesc[j] = RhsDesc{d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.nslices, d.n, ntot, d.d_hub};
         centre[j] = d.trace / (double)d.n;
         ntot += d.n;
         n = std::max(n, d.n);
@@ -428,6 +564,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     bool pairable = K >= 2;
     for (int64_t j = 0; j + 1 < K && pairable && !rq.Hj.empty(); j += 2) pairable = rq.Hj[j] == rq.Hj[j + 1];
     s.spmv_rb = pairable ? 2 : 1;
+    for (int64_t j = 0; j < K; ++j) (hdesc[j].hub ? s.has_hub : s.has_sell) = 1;
 
     DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
         brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc, bwshift, bwslot, bUproj;
@@ -872,6 +1009,7 @@ extern "C" int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double
     g_err.clear();
     if (!H || !z || !w || !rhs_idx || !o || !E_band) return fail(SCOCG_EINVAL, "null argument");
     if (n_quad <= 0 || n_rhs <= 0) return fail(SCOCG_EINVAL, "n_quad and n_rhs must be positive");
+    if (matrix_free(H)) return fail(SCOCG_EINVAL, "density_matrix_energy needs a stored matrix");
     const DevCSR &d = H->d;
     for (int64_t j = 0; j < n_rhs; ++j)
         if (rhs_idx[j] < 0 || rhs_idx[j] >= d.n) return fail(SCOCG_EINVAL, "rhs_idx out of range");
@@ -923,6 +1061,7 @@ extern "C" int backward(scocg_tape_t tape, const double *grad_G, double *grad_va
 {
     g_err.clear();
     if (!tape || !grad_G || !grad_val) return fail(SCOCG_EINVAL, "null argument");
+    if (matrix_free(tape->H)) return fail(SCOCG_EINVAL, "backward needs a stored matrix");
     const DevCSR &d = tape->H->d;
     int64_t maxrow = 0;
     for (int64_t i = 0; i < d.n; ++i)

@@ -293,6 +293,109 @@ __device__ inline const __attribute__((address_space(1))) T *gptr(const T *p)
     return (const __attribute__((address_space(1))) T *)p;
 }
 
+// Occupations of the right neighbours: bit i of the result is bit (i + 1) mod L of c.
+__device__ inline uint32_t ring_next(uint32_t c, int L) { return ((c >> 1) | ((c & 1u) << (L - 1))) & ((1u << L) - 1u); }
+
+// Row `row` of H p for the matrix-free Hubbard operator, for RB right-hand sides whose p at
+// row c is pv[RB * c + b].  The terms are added in the column order of the stored matrix
+// (up-spin hops to lower configurations, then the down-spin row with the diagonal in its
+// place, then up-spin hops to higher configurations), so the sums are those of the stored
+// matrix's product.  Diagonal: U sum_i n_i,up n_i,dn + V sum_i n_i n_i+1 (periodic).
+// Hop entries and their gathers are fetched HUB_CHUNK at a time, so a row does not wait on
+// one table load and one gather per term.
+static constexpr int HUB_CHUNK = 8;
+
+template <int RB>
+__device__ inline void hubbard_row(const HubbardOp *hp, int64_t row, const double2 *pv, double (&ax)[RB],
+                                   double (&ay)[RB])
+{
+    const HubbardOp h = *hp;
+    // rows are below 2^31 (checked at upload): 32-bit division
+    const uint32_t dd32 = (uint32_t)h.Dd;
+    const int64_t iu = (uint32_t)row / dd32;
+    const int64_t id = row - iu * h.Dd;
+    const auto *up_ptr = gptr(h.up_ptr);
+    const auto *up_hop = gptr(h.up_hop);
+    const auto *dn_ptr = gptr(h.dn_ptr);
+    const auto *dn_hop = gptr(h.dn_hop);
+    const int32_t u0 = up_ptr[iu], u1 = up_ptr[iu + 1];
+    const int32_t d0 = dn_ptr[id], d1 = dn_ptr[id + 1];
+    const uint32_t cu = gptr(h.up_conf)[iu], cd = gptr(h.dn_conf)[id];
+    double2 pd[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) pd[b] = pv[(int64_t)RB * row + b];
+    const int on = __popc(cu & cd);
+    const int inter = __popc(cu & ring_next(cu, h.L)) + __popc(cd & ring_next(cd, h.L)) +
+                      __popc(cu & ring_next(cd, h.L)) + __popc(cd & ring_next(cu, h.L));
+    const double diag = h.U * (double)on + h.V * (double)inter;
+    auto hop_val = [&](uint32_t e) { return (e >> 31) ? h.t : -h.t; };
+    auto add = [&](double v, const double2 (&pc)[RB]) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            ax[b] = fma(v, pc[b].x, ax[b]);
+            ay[b] = fma(v, pc[b].y, ay[b]);
+        }
+    };
+    // up-spin hops in order; `low` selects those to lower configurations (a < iu), which
+    // come first in the sorted list, else the rest
+    int32_t k = u0;
+    auto up_terms = [&](bool low) {
+        while (k < u1) {
+            uint32_t e[HUB_CHUNK];
+            bool ok[HUB_CHUNK];
+            double2 pc[HUB_CHUNK][RB];
+#pragma unroll
+            for (int m = 0; m < HUB_CHUNK; ++m) {
+                e[m] = (k + m < u1) ? up_hop[k + m] : 0xffffffffu;
+                const int64_t a = e[m] & 0x7fffffffu;
+                ok[m] = k + m < u1 && (!low || a < iu);
+                if (ok[m]) {
+#pragma unroll
+                    for (int b = 0; b < RB; ++b) pc[m][b] = pv[(int64_t)RB * (a * h.Dd + id) + b];
+                }
+            }
+            int used = 0;
+#pragma unroll
+            for (int m = 0; m < HUB_CHUNK; ++m) {
+                if (ok[m] && used == m) {
+                    add(hop_val(e[m]), pc[m]);
+                    ++used;
+                }
+            }
+            k += used;
+            if (used < HUB_CHUNK) break;
+        }
+    };
+    up_terms(true);
+    // the down-spin row with the diagonal at its place (before the first hop to a higher index)
+    bool diag_done = false;
+    for (int32_t m0 = d0; m0 < d1; m0 += HUB_CHUNK) {
+        uint32_t e[HUB_CHUNK];
+        double2 pc[HUB_CHUNK][RB];
+#pragma unroll
+        for (int m = 0; m < HUB_CHUNK; ++m) {
+            e[m] = (m0 + m < d1) ? dn_hop[m0 + m] : 0u;
+            if (m0 + m < d1) {
+                const int64_t bcol = e[m] & 0x7fffffffu;
+#pragma unroll
+                for (int b = 0; b < RB; ++b) pc[m][b] = pv[(int64_t)RB * (iu * h.Dd + bcol) + b];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < HUB_CHUNK; ++m) {
+            if (m0 + m < d1) {
+                if (!diag_done && (int64_t)(e[m] & 0x7fffffffu) > id) {
+                    add(diag, pd);
+                    diag_done = true;
+                }
+                add(hop_val(e[m]), pc[m]);
+            }
+        }
+    }
+    if (!diag_done) add(diag, pd);
+    up_terms(false);
+}
+
 // Slots of a slice processed per batch: the column and value loads of SPMV_CHUNK slots are
 // issued together, then their gathers, so each wave has many loads in flight.
 static constexpr int SPMV_CHUNK = 8;
@@ -301,7 +404,10 @@ static constexpr int SPMV_CHUNK = 8;
 // the column and value of each slot are loaded once and serve all RB gathers.  The products
 // are summed in slot order in every configuration, so a rhs gets the same bits alone or in
 // a batch.
-template <int RB>
+// HUB: the instance for right-hand sides with a matrix-free Hubbard operator (a separate
+// kernel, so the stored-matrix instance keeps its small register footprint); each instance
+// leaves the other kind's right-hand sides alone.
+template <int RB, bool HUB>
 __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
 {
     __shared__ double2 sh2[WG];
@@ -322,6 +428,7 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
     }
     if (!any) return;
     const RhsDesc d = s.desc[j0];
+    if ((d.hub != nullptr) != HUB) return;
     const int lane = threadIdx.x & 63;
     // one 64-row slice per wave (wave-uniform, so its bookkeeping lives in scalar registers)
     const int64_t slice = rb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -335,7 +442,9 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
         ax[b] = 0;
         ay[b] = 0;
     }
-    if (slice < d.nslices) {
+    if (HUB) {
+        if (row < d.n) hubbard_row<RB>(d.hub, row, pv, ax, ay);
+    } else if (slice < d.nslices) {
         const int64_t off = gptr(d.slice_ptr)[slice];
         const int w = gptr(d.slice_w)[slice];
         const auto *colp = gptr(d.ell_col) + off + lane;
@@ -794,15 +903,24 @@ __global__ void __launch_bounds__(WG) k_true_res_part(const RhsDesc *__restrict_
     const double2 *x = X + M * d.voff + k * d.n;
     double e = 0;
     if (slice < d.nslices) {
-        const int64_t off = d.slice_ptr[slice];
-        const int w = d.slice_w[slice];
         double ax = 0, ay = 0;
-        for (int q = 0; q < w; ++q) {
-            const int col = d.ell_col[off + (int64_t)q * 64 + lane];
-            const double v = d.ell_val[off + (int64_t)q * 64 + lane];
-            const double2 xc = x[col];
-            ax = fma(v, xc.x, ax);
-            ay = fma(v, xc.y, ay);
+        if (d.hub) {
+            if (row < d.n) {
+                double hx[1] = {0}, hy[1] = {0};
+                hubbard_row<1>(d.hub, row, x, hx, hy);
+                ax = hx[0];
+                ay = hy[0];
+            }
+        } else {
+            const int64_t off = d.slice_ptr[slice];
+            const int w = d.slice_w[slice];
+            for (int q = 0; q < w; ++q) {
+                const int col = d.ell_col[off + (int64_t)q * 64 + lane];
+                const double v = d.ell_val[off + (int64_t)q * 64 + lane];
+                const double2 xc = x[col];
+                ax = fma(v, xc.x, ax);
+                ay = fma(v, xc.y, ay);
+            }
         }
         if (row < d.n) {
             double2 b;
@@ -971,8 +1089,14 @@ hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
     if (RB == 2) hipLaunchKernelGGL(k_pupd<2>, grid2(s.nblk, G), dim3(WG), 0, st, s);
     else hipLaunchKernelGGL(k_pupd<1>, grid2(s.nblk, G), dim3(WG), 0, st, s);
     const int64_t nwg = G < 8 ? s.nblk * G : s.nblk * 8 * ((G + 7) / 8);
-    if (RB == 2) hipLaunchKernelGGL(k_spmv<2>, dim3((unsigned)nwg), dim3(WG), 0, st, s);
-    else hipLaunchKernelGGL(k_spmv<1>, dim3((unsigned)nwg), dim3(WG), 0, st, s);
+    if (s.has_sell) {
+        if (RB == 2) hipLaunchKernelGGL((k_spmv<2, false>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
+        else hipLaunchKernelGGL((k_spmv<1, false>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
+    }
+    if (s.has_hub) {
+        if (RB == 2) hipLaunchKernelGGL((k_spmv<2, true>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
+        else hipLaunchKernelGGL((k_spmv<1, true>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
+    }
     hipLaunchKernelGGL(k_alpha, dim3((unsigned)s.K), dim3(WG), 0, st, s);
     hipLaunchKernelGGL(k_rupd, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
     hipLaunchKernelGGL(k_beta, dim3((unsigned)s.K), dim3(WG), 0, st, s);

@@ -65,6 +65,23 @@ struct SeedState {
 
 enum PairStatus : int32_t { PAIR_OK = 0, PAIR_BREAKDOWN = 4, PAIR_NOCONV = 5 };
 
+// ---- matrix-free extended Hubbard ring (Sec. 4.2 model class) ----
+// H = T_up (x) 1 + 1 (x) T_dn + D in the occupation-number basis, row = i_up * Dd + i_dn.
+// A hop entry is the target configuration's index with bit 31 set when its value is +t
+// (else -t); the hops of a configuration are sorted by target.
+struct HubbardOp {
+    const int32_t *up_ptr;   // [Du + 1]
+    const uint32_t *up_hop;  // hops of the up-spin configurations
+    const uint32_t *up_conf; // [Du] occupation bit patterns
+    const int32_t *dn_ptr;   // [Dd + 1]
+    const uint32_t *dn_hop;
+    const uint32_t *dn_conf; // [Dd]
+    int64_t Dd;              // down-spin configurations (the fast index of a row)
+    double t, U, V;
+    int32_t L;               // ring sites
+    int32_t pad;
+};
+
 // ---- device-side matrix ----
 struct DevCSR {
     int64_t n, nnz;
@@ -83,6 +100,8 @@ struct DevCSR {
     int64_t *h_col;
     int64_t *h_ell_src;   // [ell_nnz] CSR position of each slot (host)
     int max_w;            // widest slice
+    HubbardOp *d_hub;     // matrix-free operator (device struct), or null for a stored matrix
+    void *d_hub_tables;   // device tables the operator points into
 };
 
 // ---- per right-hand side: its matrix and where its vectors live ----
@@ -97,7 +116,7 @@ struct RhsDesc {
     int64_t nslices;
     int64_t n;
     int64_t voff;
-    int64_t pad;
+    const HubbardOp *hub;  // matrix-free operator instead of the slices, or null
 };
 
 // ---- launch wrappers (kernels.hip) ----
@@ -135,6 +154,7 @@ struct SolveDev {
     int shifts_per_wg;
     int zper;                  // 1: one shift per rhs (M = 1, z has K entries), used by refinement
     int spmv_rb;               // right-hand sides per SpMV thread (2: each rhs pair 2i, 2i+1 shares its matrix)
+    int has_sell, has_hub;     // some rhs has a stored matrix / a matrix-free Hubbard operator
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
 };
 

@@ -1,0 +1,94 @@
+"""Matrix-free extended Hubbard ring (hubbard_upload) against the stored sector matrix.
+
+The stored matrix comes from `workloads.hubbard_ring`, an independent construction of the
+same sector (Python, numpy); the operator builds its hopping tables in the library.  Equal
+products make every solve bit for bit equal, which pins the basis order, the fermion signs
+and the diagonal of both.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import hubbard_ring
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _S():
+    import paper_0802_0748_amd as S
+
+    return S
+
+
+def _rhs(n, k, seed):
+    rng = np.random.default_rng(seed)
+    B = rng.normal(size=(k, n)) + 1j * rng.normal(size=(k, n))
+    return B / np.linalg.norm(B, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("L,nu,nd", [(6, 3, 3), (8, 4, 3), (10, 5, 5), (9, 2, 7)])
+def test_operator_equals_stored_matrix_bitwise(L, nu, nd):
+    S = _S()
+    Hc = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    Hm = S.Hamiltonian.from_csr(Hc)
+    Ho = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    assert Ho.n == Hc.n and Ho.nnz == Hc.nnz
+    z = np.linspace(-6, 12, 7) + 0.1j
+    B = torch.from_numpy(_rhs(Hc.n, 3, L)).cuda()
+    Xm, _, _, _ = S.shifted_cocg_solve(Hm, z, B, fixed_iter=40, seed_index=0)
+    Xo, _, _, _ = S.shifted_cocg_solve(Ho, z, B, fixed_iter=40, seed_index=0)
+    assert np.array_equal(Xo.cpu().numpy(), Xm.cpu().numpy())
+
+
+def test_operator_production_solve_matches_stored_matrix_and_oracle():
+    """Tolerance-stopped solve with seed switching: same bits as the stored matrix (the
+    seed, its trace-based choice and every switch agree), FP64 true residuals at the
+    tolerance, and a sampled pair within the residual bound of the oracle's solution."""
+    S = _S()
+    L, nu, nd = 10, 5, 4
+    Hc = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    Hm = S.Hamiltonian.from_csr(Hc)
+    Ho = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    z = np.linspace(-10, 20, 12) + 1j * np.linspace(0.05, 0.4, 12)
+    Bn = _rhs(Hc.n, 2, 3)
+    B = torch.from_numpy(Bn).cuda()
+    tol = 1e-9
+    Xo, repo, _, rco = S.shifted_cocg_solve(Ho, z, B, tol=tol, max_iter=8000, check_true=True)
+    Xm, repm, _, rcm = S.shifted_cocg_solve(Hm, z, B, tol=tol, max_iter=8000)
+    assert rco == 0 and rcm == 0
+    assert np.array_equal(repo["iters"], repm["iters"])
+    assert np.array_equal(Xo.cpu().numpy(), Xm.cpu().numpy())
+    assert repo["res_true"].max() < 20 * tol
+    j, k = 1, 5
+    ref = O.cocg(Hc, z[k], Bn[j], tol=tol, max_iter=20000)
+    r_orc = O.true_residual(Hc, z[k], ref["x"], Bn[j])
+    bound = (repo["res_true"][j, k] + r_orc) / z[k].imag
+    assert np.linalg.norm(Xo[j, k].cpu().numpy() - ref["x"]) <= bound * (1 + 1e-6)
+
+
+def test_operator_greens_diag_equals_stored_matrix():
+    S = _S()
+    L, nu, nd = 8, 4, 4
+    Hc = hubbard_ring(L, nu, nd, t=1.0, U=2.0, V=0.5)
+    Hm = S.Hamiltonian.from_csr(Hc)
+    Ho = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=2.0, V=0.5)
+    z = np.linspace(-6, 8, 10) + 0.2j
+    rhs = [0, 7, 1000, Hc.n - 1]
+    Gm, _, _, _ = S.greens_diag(Hm, z, rhs, tol=1e-10, max_iter=6000)
+    Go, _, _, _ = S.greens_diag(Ho, z, rhs, tol=1e-10, max_iter=6000)
+    assert np.array_equal(Go.cpu().numpy(), Gm.cpu().numpy())
+
+
+def test_operator_rejects_calls_that_need_stored_entries():
+    S = _S()
+    Ho = S.Hamiltonian.hubbard(6, 3, 3)
+    with pytest.raises(RuntimeError):
+        Ho.update_values(np.zeros(Ho.nnz))
+    z, w = S.contour(-20.0, 0.0, 8)
+    with pytest.raises(RuntimeError):
+        S.density_matrix_energy(Ho, z, w, rhs_idx=[0, 1])
+    for bad in [(2, 1, 1), (8, 9, 1), (8, 1, -1), (31, 1, 1)]:
+        with pytest.raises(RuntimeError):
+            S.Hamiltonian.hubbard(*bad)
