@@ -317,6 +317,19 @@ def update_roofline(upd_ms, upd_bytes, upd_launches, workload):
             "bytes_per_launch": upd_bytes / max(upd_launches, 1)}
 
 
+def hot_path(update_bytes, seed_iterations, n, elapsed, matrix_bytes=0, sweeps=0):
+    """Whole hot path (seed SpMV and vector updates + deferred shift update) as one HBM figure:
+    the update kernel's device-counted bytes plus 8 complex FP64 vectors of n rows per seed
+    iteration (p update: r, p read, p written; SpMV: p gathered, q written; residual: r, q
+    read, r written) plus the stored matrix once per sweep of the batch, over the wall time of
+    the timed solves.  The update runs concurrently with the next block's iterations, so this,
+    not the update kernel alone, is what the step's time is bound by."""
+    nbytes = update_bytes + seed_iterations * 8 * 16 * n + matrix_bytes * sweeps
+    gbs = nbytes / 1e9 / elapsed
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "bytes": nbytes, "seconds": elapsed}
+
+
 def bench_batch(args, S, torch):
     """Disordered cubic lattices of uneven size (L in 24..64, W in {1, 4, 8}), 32 unit RHS per
     lattice, 512 shifts eta = 0.002, FP32 directions / FP64 scalars, all in one solve
@@ -491,7 +504,7 @@ def main():
         print(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s rc={rc}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     upd_ms = upd_bytes = 0.0
-    upd_launches = 0
+    upd_launches = seed_iters = 0
     converged = 0
     iters = None
     t0 = time.perf_counter()
@@ -502,6 +515,7 @@ def main():
         upd_ms += t["update_ms"]
         upd_bytes += t["update_bytes"]
         upd_launches += t["update_launches"]
+        seed_iters += t["iterations"]
         converged += int((rep["status"] == 0).sum())
         iters = rep["iters"]
         print(f"[bench] step {s}: {time.perf_counter() - ts:.2f} s rc={rc} converged "
@@ -529,6 +543,8 @@ def main():
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
                    "block": args.block or 24, "iterations_per_step": int(np.max(iters))},
         "roofline": update_roofline(upd_ms, upd_bytes, upd_launches, args.workload),
+        "hot_path": hot_path(upd_bytes, seed_iters, n, elapsed, 0 if args.matrix_free else 12 * int(p.H.nnz),
+                             args.steps * int(np.max(iters))),
     }
     if not args.no_cpu_baseline:
         # the oracle's cost per iteration grows with shifts x rows: keep the sample near

@@ -59,13 +59,15 @@ struct DevBuf {
 
 struct GraphPair {
     hipStream_t cap = nullptr;
-    hipGraph_t ga = nullptr, gb = nullptr;
-    hipGraphExec_t ea = nullptr, eb = nullptr;
+    hipGraph_t ga[2] = {nullptr, nullptr}, gb = nullptr;
+    hipGraphExec_t ea[2] = {nullptr, nullptr}, eb = nullptr;
     ~GraphPair()
     {
-        if (ea) (void)hipGraphExecDestroy(ea);
+        for (int q = 0; q < 2; ++q) {
+            if (ea[q]) (void)hipGraphExecDestroy(ea[q]);
+            if (ga[q]) (void)hipGraphDestroy(ga[q]);
+        }
         if (eb) (void)hipGraphExecDestroy(eb);
-        if (ga) (void)hipGraphDestroy(ga);
         if (gb) (void)hipGraphDestroy(gb);
         if (cap) (void)hipStreamDestroy(cap);
     }
@@ -567,7 +569,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     for (int64_t j = 0; j < K; ++j) (hdesc[j].hub ? s.has_hub : s.has_sell) = 1;
 
     DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
-        brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc, bwshift, bwslot, bUproj;
+        brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc, bwshift, bwslot, bUproj, bblk;
     auto A = [&](DevBuf &b, size_t bytes) -> hipError_t { return b.alloc(bytes); };
     hipError_t e = hipSuccess;
 #define ALLOC(buf, bytes)                                                                                  \
@@ -579,7 +581,8 @@ int solve(SolveRequest &rq, hipStream_t st)
     } while (0)
     ALLOC(bz, nz * sizeof(double2));
     ALLOC(bseed, K * sizeof(SeedState));
-    ALLOC(bring, (size_t)(TB + 1) * vec * sizeof(double2));
+    const int R = 2 * TB + 1;  // ring slots: one block's update overlaps the next block's iterations
+    ALLOC(bring, (size_t)R * vec * sizeof(double2));
     ALLOC(bp, 2 * vec * sizeof(double2));
     ALLOC(bq, vec * sizeof(double2));
     ALLOC(bP, (size_t)Mst * ntot * esz);
@@ -602,11 +605,13 @@ int solve(SolveRequest &rq, hipStream_t st)
     ALLOC(biters, KM * sizeof(int32_t));
     ALLOC(bpst, KM * sizeof(int32_t));
     ALLOC(bact, KM * sizeof(int32_t));
-    ALLOC(bnact, KM * sizeof(int32_t));
+    ALLOC(bnact, 2 * KM * sizeof(int32_t));
+    ALLOC(bblk, 2 * (size_t)K * 4 * sizeof(int32_t));
     ALLOC(bah, K * TB * sizeof(double2));
     ALLOC(bbh, K * TB * sizeof(double2));
     ALLOC(brn, K * TB * sizeof(double));
-    ALLOC(bcoef, KM * TB * 2 * (o.precision == 0 ? sizeof(double2) : sizeof(float2)));
+    const size_t coef_bytes = KM * TB * 2 * (o.precision == 0 ? sizeof(double2) : sizeof(float2));
+    ALLOC(bcoef, 2 * coef_bytes);
     ALLOC(bp2, K * s.nblk * sizeof(double2));
     ALLOC(bp1, K * s.nblk * sizeof(double));
     ALLOC(bcnt, K * sizeof(uint32_t));
@@ -617,6 +622,8 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.z = bz.as<double2>();
     s.seed = bseed.as<SeedState>();
     s.ring = bring.as<double2>();
+    s.R = R;
+    s.blk = bblk.as<int32_t>();
     s.p = bp.as<double2>();
     s.q = bq.as<double2>();
     s.P = bP.ptr;
@@ -658,6 +665,8 @@ int solve(SolveRequest &rq, hipStream_t st)
         if (!need_full) HIPCHK(hipMemcpyAsync(bprow.ptr, rq.unit_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
     }
     HIPCHK(launch_zero(bcnt.ptr, K * sizeof(uint32_t), st));
+    HIPCHK(launch_zero(bnact.ptr, 2 * KM * sizeof(int32_t), st));
+    HIPCHK(launch_zero(bblk.ptr, 2 * (size_t)K * 4 * sizeof(int32_t), st));
     HIPCHK(launch_zero(bstats.ptr, 2 * sizeof(unsigned long long), st));
     if (need_full) HIPCHK(launch_zero(s.X, (size_t)M * ntot * esz, st));
     HIPCHK(launch_zero(s.p, 2 * vec * sizeof(double2), st));
@@ -675,74 +684,131 @@ int solve(SolveRequest &rq, hipStream_t st)
             for (auto e : *v) (void)hipEventDestroy(e);
         }
     } evl{&evs};
-    std::vector<hipEvent_t> fev;
-    if (g_profiling) {
-        fev.resize(2 * std::max(1, 64 / TB));
-        for (auto &e : fev) {
-            HIPCHK(hipEventCreate(&e));
-            evs.push_back(e);
-        }
-    }
+    auto new_event = [&](hipEvent_t &e, unsigned flags) -> hipError_t {
+        hipError_t r = hipEventCreateWithFlags(&e, flags);
+        if (r == hipSuccess) evs.push_back(e);
+        return r;
+    };
 
-    // Each block is three launches: the captured seed iterations and shift scalars (graph A),
-    // the deferred update (timed with events when profiling), and the captured end-of-block
-    // decisions (graph B).  Graphs are captured on a private stream and replayed on `st`.
+    // The deferred update of block c runs on its own stream, overlapping the seed iterations of
+    // block c + 1 (which write other ring slots and the other parity's coefficient buffers);
+    // block c + 2 waits for it.  A seed switch decided at the end of block c waits out block
+    // c + 1 and is applied at the start of block c + 2, after the update of block c.
+    struct FlushStream {
+        hipStream_t sf = nullptr;
+        bool own = false;
+        ~FlushStream()
+        {
+            if (own && sf) {
+                (void)hipStreamSynchronize(sf);
+                (void)hipStreamDestroy(sf);
+            }
+        }
+    } fs;
+    if (o.serial) {
+        fs.sf = st;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&fs.sf, hipStreamNonBlocking));
+        fs.own = true;
+    }
+    const hipStream_t sf = fs.sf;
+    hipEvent_t evPS[2], evFL[2];
+    for (int q = 0; q < 2; ++q) {
+        HIPCHK(new_event(evPS[q], hipEventDisableTiming));
+        HIPCHK(new_event(evFL[q], hipEventDisableTiming));
+    }
+    // per-parity views of the double-buffered per-block arrays
+    SolveDev sp[2] = {s, s};
+    for (int q = 0; q < 2; ++q) {
+        sp[q].coef = (char *)bcoef.ptr + q * coef_bytes;
+        sp[q].nact = bnact.as<int32_t>() + q * KM;
+        sp[q].blk = bblk.as<int32_t>() + q * (size_t)K * 4;
+    }
+    // update-kernel timing: a ring of event pairs on the update stream, read back lazily
+    constexpr int NE = 8;
+    hipEvent_t fev[2 * NE] = {};
+    bool fev_pending[NE] = {};
+    if (g_profiling)
+        for (int q = 0; q < 2 * NE; ++q) HIPCHK(new_event(fev[q], hipEventDefault));
+    auto collect = [&](int slot) -> hipError_t {
+        if (!fev_pending[slot]) return hipSuccess;
+        hipError_t r = hipEventSynchronize(fev[2 * slot + 1]);
+        if (r != hipSuccess) return r;
+        float ms = 0;
+        r = hipEventElapsedTime(&ms, fev[2 * slot], fev[2 * slot + 1]);
+        if (r != hipSuccess) return r;
+        g_timing.update_ms += ms;
+        g_timing.update_launches += 1;
+        fev_pending[slot] = false;
+        return hipSuccess;
+    };
+
+    // Each block: the captured switch application, seed iterations and shift scalars (graph
+    // A, one per parity) on `st`; the deferred update on the update stream; the captured
+    // end-of-block decisions (graph B) on `st`.  Graphs are captured on a private stream.
     GraphPair gr;
     const bool use_graph = !o.no_graph;
     if (use_graph) {
         HIPCHK(hipStreamCreateWithFlags(&gr.cap, hipStreamNonBlocking));
+        for (int q = 0; q < 2; ++q) {
+            HIPCHK(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
+            HIPCHK(launch_switch_vectors(sp[q], gr.cap));
+            for (int t = 0; t < TB; ++t) HIPCHK(launch_seed_iteration(sp[q], gr.cap));
+            HIPCHK(launch_pair_scalars(sp[q], gr.cap));
+            HIPCHK(hipStreamEndCapture(gr.cap, &gr.ga[q]));
+            HIPCHK(hipGraphInstantiate(&gr.ea[q], gr.ga[q], nullptr, nullptr, 0));
+        }
         HIPCHK(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
-        for (int t = 0; t < TB; ++t) HIPCHK(launch_seed_iteration(s, gr.cap));
-        HIPCHK(launch_pair_scalars(s, gr.cap));
-        HIPCHK(hipStreamEndCapture(gr.cap, &gr.ga));
-        HIPCHK(hipGraphInstantiate(&gr.ea, gr.ga, nullptr, nullptr, 0));
-        HIPCHK(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
-        HIPCHK(launch_block_finalize(s, gr.cap));
-        HIPCHK(launch_switch_vectors(s, gr.cap));
+        HIPCHK(launch_block_finalize(sp[0], gr.cap));
         HIPCHK(hipStreamEndCapture(gr.cap, &gr.gb));
         HIPCHK(hipGraphInstantiate(&gr.eb, gr.gb, nullptr, nullptr, 0));
     }
     // host checks the stop condition every `per_sync` blocks (about 64 iterations); blocks
     // launched after every rhs has stopped return immediately
     const int per_sync = std::max(1, 64 / TB);
-    // worst case: every block advances one rhs by >= 1 iteration or finishes / switches one rhs
-    const int64_t max_blocks = (int64_t)K * ((int64_t)limit + 2 * M + 4) + 8 + per_sync;
+    // worst case: every block advances one rhs by >= 1 iteration, or finishes, switches or
+    // waits out a switch for one rhs
+    const int64_t max_blocks = (int64_t)K * ((int64_t)limit + 4 * M + 8) + 8 + per_sync;
     int64_t blocks = 0;
     bool done = false;
     while (!done) {
         for (int b = 0; b < per_sync; ++b) {
+            const int par = (int)(blocks & 1);
+            if (blocks >= 2) HIPCHK(hipStreamWaitEvent(st, evFL[par], 0));
             if (use_graph) {
-                HIPCHK(hipGraphLaunch(gr.ea, st));
+                HIPCHK(hipGraphLaunch(gr.ea[par], st));
             } else {
-                for (int t = 0; t < TB; ++t) HIPCHK(launch_seed_iteration(s, st));
-                HIPCHK(launch_pair_scalars(s, st));
+                HIPCHK(launch_switch_vectors(sp[par], st));
+                for (int t = 0; t < TB; ++t) HIPCHK(launch_seed_iteration(sp[par], st));
+                HIPCHK(launch_pair_scalars(sp[par], st));
             }
-            if (g_profiling) HIPCHK(hipEventRecord(fev[2 * b], st));
-            HIPCHK(launch_flush(s, st));
-            if (g_profiling) HIPCHK(hipEventRecord(fev[2 * b + 1], st));
-            if (use_graph) {
-                HIPCHK(hipGraphLaunch(gr.eb, st));
-            } else {
-                HIPCHK(launch_block_finalize(s, st));
-                HIPCHK(launch_switch_vectors(s, st));
+            HIPCHK(hipEventRecord(evPS[par], st));
+            HIPCHK(hipStreamWaitEvent(sf, evPS[par], 0));
+            const int slot = (int)(blocks % NE);
+            if (g_profiling) {
+                HIPCHK(collect(slot));
+                HIPCHK(hipEventRecord(fev[2 * slot], sf));
             }
+            HIPCHK(launch_flush(sp[par], sf));
+            if (g_profiling) {
+                HIPCHK(hipEventRecord(fev[2 * slot + 1], sf));
+                fev_pending[slot] = true;
+            }
+            HIPCHK(hipEventRecord(evFL[par], sf));
+            if (use_graph) HIPCHK(hipGraphLaunch(gr.eb, st));
+            else HIPCHK(launch_block_finalize(sp[par], st));
             ++blocks;
         }
         HIPCHK(hipMemcpyAsync(hs, s.seed, K * sizeof(SeedState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (g_profiling) {
-            for (int b = 0; b < per_sync; ++b) {
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, fev[2 * b], fev[2 * b + 1]));
-                g_timing.update_ms += ms;
-                g_timing.update_launches += 1;
-            }
-        }
         done = true;
         for (int64_t j = 0; j < K; ++j)
             if (hs[j].status != SEED_STOPPED) done = false;
         if (blocks > max_blocks) return fail(SCOCG_EHIP, "iteration driver did not terminate");
     }
+    HIPCHK(hipStreamSynchronize(sf));
+    if (g_profiling)
+        for (int q = 0; q < NE; ++q) HIPCHK(collect(q));
     int64_t iters_total = 0, switches = 0;
     for (int64_t j = 0; j < K; ++j) {
         iters_total += hs[j].iter;

@@ -56,12 +56,13 @@ __device__ inline void apply_steps(const V *coef, const int64_t (&cp)[NP], const
 }
 
 template <int TB, typename V, int NP, bool PROJ>
-__global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed, const double2 *__restrict__ ring,
+__global__ void __launch_bounds__(WG) k_flush(const int32_t *__restrict__ blk, const double2 *__restrict__ ring,
                                               const V *__restrict__ coef, const int32_t *__restrict__ nact,
                                               V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
                                               const int64_t *__restrict__ proj_row,
                                               const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
-                                              int ngroups, const int32_t *__restrict__ wshift, int64_t Mst)
+                                              int ngroups, const int32_t *__restrict__ wshift, int64_t Mst,
+                                              int R)
 {
     // Row blocks run fastest in dispatch order, so the concurrently running workgroups of one
     // shift group stream long contiguous stretches of each pair's x and u.  (Dealing the shift
@@ -70,10 +71,11 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     const int64_t j = blockIdx.y / ngroups;
     const int g = blockIdx.y % ngroups;
     const int64_t rb = blockIdx.x;
-    const int ns = seed[j].step;
+    // this block's steps, ring slot of its first residual, first block (x, u start at 0)
+    const int ns = blk[4 * j + 0];
     if (ns == 0) return;
-    const int base = seed[j].base;
-    const bool fresh = seed[j].iter == ns;
+    const int base = blk[4 * j + 1];
+    const bool fresh = blk[4 * j + 2] != 0;
     const int64_t n = desc[j].n;
     const int64_t voff = desc[j].voff;
     const int64_t row = rb * WG + threadIdx.x;
@@ -90,7 +92,7 @@ __global__ void __launch_bounds__(WG) k_flush(const SeedState *__restrict__ seed
     V r[TB];
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
-        if (t < ns) r[t] = to_v<V>(ring[(int64_t)((base + t) % (TB + 1)) * ntot + voff + row]);
+        if (t < ns) r[t] = to_v<V>(ring[(int64_t)((base + t) % R) * ntot + voff + row]);
         else r[t] = to_v<V>(cmk(0, 0));
     }
     X += M * voff;
@@ -166,12 +168,12 @@ static hipError_t flush_v(const SolveDev &s, hipStream_t st)
     const dim3 g((unsigned)s.nblk, (unsigned)(s.K * ng));
     const V *coef = (const V *)s.coef;
     if (s.Xproj)
-        hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)nullptr,
-                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst);
+        hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.blk, s.ring, coef, s.nact, (V *)nullptr,
+                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst, s.R);
     else
-        hipLaunchKernelGGL((k_flush<TB, V, NP, false>), g, dim3(WG), 0, st, s.seed, s.ring, coef, s.nact, (V *)s.X,
+        hipLaunchKernelGGL((k_flush<TB, V, NP, false>), g, dim3(WG), 0, st, s.blk, s.ring, coef, s.nact, (V *)s.X,
                            (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng,
-                           (const int32_t *)nullptr, s.M);
+                           (const int32_t *)nullptr, s.M, s.R);
     return hipGetLastError();
 }
 

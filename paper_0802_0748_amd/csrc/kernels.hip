@@ -3,7 +3,7 @@
 // flush.hip.
 //
 // Data layout in HBM (n rows, K right-hand sides, M shifts; see RhsDesc for mixed sizes):
-//   seed vectors r (ring of TB+1 slots), q : one contiguous vector per rhs; p likewise, or
+//   seed vectors r (ring of 2 TB + 1 slots), q : one contiguous vector per rhs; p likewise, or
 //                                             two rhs interleaved (see p_index)
 //   per-shift vectors x_k, u_k                                : pair-major, FP64 or FP32 complex
 //   H : 64-row slices, each slice stored column-slot-major (slot k of the 64 rows is
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(WG) k_init(SolveDev s, const double2 *__restri
         st.n_active = nb > 0 ? (int32_t)s.M : 0;
         st.switches = 0;
         st.limit = limit;
-        st.pad = 0;
+        st.sw_age = 0;
         s.seed[j] = st;
     }
     reset_counter(s.cnt, j);
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(WG) k_pupd(SolveDev s)
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
         if (run[b]) {
-            const double2 r = ring_slot(s, (st[b].base + st[b].step) % (s.TB + 1), s.desc[j0 + b])[row];
+            const double2 r = ring_slot(s, (st[b].base + st[b].step) % s.R, s.desc[j0 + b])[row];
             pv[b] = cfma(st[b].beta_prev, pv[b], r);
         }
     }
@@ -520,8 +520,8 @@ __global__ void __launch_bounds__(WG) k_rupd(SolveDev s)
     if (!seed_running(st, s.TB)) return;
     const RhsDesc d = s.desc[j];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
-    const int slot = (st.base + st.step) % (s.TB + 1);
-    const int nslot = (slot + 1) % (s.TB + 1);
+    const int slot = (st.base + st.step) % s.R;
+    const int nslot = (slot + 1) % s.R;
     const double2 a = s.ahist[j * s.TB + st.step];
     double2 rr = cmk(0, 0);
     double nn = 0;
@@ -640,7 +640,7 @@ __device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t
         const int64_t at = s.desc[j].voff + s.proj_row[j];
         V x = to_v<V>(s.Xproj[pair]), u = to_v<V>(s.Uproj[pair]);
         for (int t = 0; t < na; ++t) {
-            const V r = to_v<V>(s.ring[(int64_t)((st.base + t) % (s.TB + 1)) * s.ntot + at]);
+            const V r = to_v<V>(s.ring[(int64_t)((st.base + t) % s.R) * s.ntot + at]);
             u = cfma(cf[2 * t + 1], u, r);
             x = cfma(cf[2 * t + 0], u, x);
         }
@@ -669,6 +669,14 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
     __shared__ unsigned long long shb[WG];
     __shared__ unsigned int shc[WG];
     const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (pair < s.K * s.M && pair % s.M == 0) {
+        // what the deferred update of this block needs, fixed before the block ends
+        const int64_t j = pair / s.M;
+        const SeedState st = s.seed[j];
+        s.blk[4 * j + 0] = st.step;
+        s.blk[4 * j + 1] = st.base;
+        s.blk[4 * j + 2] = st.iter == st.step ? 1 : 0;
+    }
     const unsigned long long b = pair < s.K * s.M ? pair_scalars_one<V>(s, pair) : 0ull;
     shb[threadIdx.x] = b;
     shc[threadIdx.x] = b > 0 ? 1u : 0u;
@@ -748,26 +756,33 @@ __global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
             mb = 1;
         } else if (st.status == SEED_PAUSED) {
             sw = sh_idx[0];
-            w.status = SEED_RUNNING;
             if (sw < 0) {
                 // no stored direction is left to switch to: iterating the converged seed further
                 // would let rounding break the collinearity of the residuals, so the pairs still
                 // active stop here, unconverged
                 w.status = SEED_STOPPED;
                 mb = 2;
+            } else if (sw == st.seed) {
+                w.status = SEED_RUNNING;
+            } else {
+                // the scalars switch now; the vectors once this block's update is done
+                w.status = SEED_SWITCH;
+                w.sw_age = 0;
             }
+        } else if (st.status == SEED_SWITCH) {
+            w.sw_age = 1;
         } else if (st.status == SEED_LIMIT) {
             w.status = SEED_STOPPED;
         }
         // the deferred update read the block's residual history once per row
         if (st.step > 0)
             atomicAdd(&s.stats[0], (unsigned long long)st.step * 16ull * (unsigned long long)s.desc[j].n);
-        w.base = (st.base + st.step) % (s.TB + 1);
+        w.base = (st.base + st.step) % s.R;
         w.step = 0;
         w.n_active = n_active;
         w.a0 = st.alpha_prev;
         w.b0 = st.beta_prev;
-        w.sw_target = -1;
+        if (st.status != SEED_SWITCH) w.sw_target = -1;
         s.seed[j] = w;
         dec_switch = (sw >= 0 && sw != st.seed) ? sw : -1;
         dec_brk = mb;
@@ -819,7 +834,9 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
     __shared__ double2 sh2[WG];
     const int64_t j = blockIdx.y;
     const SeedState st = s.seed[j];
-    if (st.sw_target < 0) return;
+    // switched one block end after the decision, when the update of the rhs's last block
+    // (launched before that block end) has finished
+    if (st.status != SEED_SWITCH || st.sw_age < 1) return;
     const RhsDesc d = s.desc[j];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     double2 rr = cmk(0, 0);
@@ -858,6 +875,8 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
     if (threadIdx.x == 0) {
         s.seed[j].rho = rho;
         s.seed[j].sw_target = -1;
+        s.seed[j].sw_age = 0;
+        s.seed[j].status = SEED_RUNNING;
     }
     reset_counter(s.cnt, j);
 }

@@ -38,7 +38,9 @@ enum SeedStatus : int32_t {
     SEED_PAUSED = 1,    // seed converged: switch at the end of this block
     SEED_LIMIT = 2,     // iteration limit reached
     SEED_STOPPED = 3,   // finished (all pairs frozen or limit)
-    SEED_BREAKDOWN = 4  // COCG breakdown
+    SEED_BREAKDOWN = 4, // COCG breakdown
+    SEED_SWITCH = 5     // switch decided; its vectors are switched once the update of the rhs's
+                        // last block has finished (the rhs sits out one block meanwhile)
 };
 
 struct SeedState {
@@ -60,7 +62,7 @@ struct SeedState {
     int32_t n_active;    // pairs still active after the last block
     int32_t switches;    // number of seed switches so far
     int32_t limit;       // iteration limit (max_iter or fixed_iter)
-    int32_t pad;
+    int32_t sw_age;      // block ends since the switch decision (its vectors are switched at 1)
 };
 
 enum PairStatus : int32_t { PAIR_OK = 0, PAIR_BREAKDOWN = 4, PAIR_NOCONV = 5 };
@@ -124,14 +126,16 @@ struct SolveDev {
     const RhsDesc *desc;       // [K]
     int64_t ntot;              // sum of n over right-hand sides (stride of one ring slot)
     int64_t n, K, M;           // n: the largest row count
-    int TB;                    // block length (ring has TB+1 slots)
+    int TB;                    // block length
+    int R;                     // ring slots, 2 TB + 1: the update of one block reads its residuals
+                               // while the next block's iterations write theirs
     int precision;             // 0 FP64 storage, 1 FP32
     int fixed;                 // fixed-iteration mode
     int switching;
     double tol;
     const double2 *z;          // [M]
     SeedState *seed;           // [K]
-    double2 *ring;             // [(TB+1)][K][n]
+    double2 *ring;             // [R][ntot]
     double2 *p, *q;            // [K][n]
     void *X, *P;               // X [K][M][n], P [K][Mst][n] (double2 or float2); X is null in projection
                                // mode.  P holds the scaled directions u_k = pi_k p_k (see k_flush)
@@ -146,7 +150,10 @@ struct SolveDev {
     int32_t *iters, *pstatus, *active, *nact; // [K*M]
     double2 *ahist, *bhist;    // [K][TB]
     double *rnhist;            // [K][TB]
-    void *coef;                // [K*M][TB][2] (a', b') as double2 (FP64) or float2 (FP32 storage)
+    void *coef;                // [K*M][TB][2] (a', b') as double2 (FP64) or float2 (FP32 storage);
+                               // coef, nact and blk are double-buffered by block parity: these
+                               // point at this block's buffers
+    int32_t *blk;              // [K][4] this block for the deferred update: steps, ring base, first block
     double2 *part2;            // [K][nblk] complex partials
     double *part1;             // [K][nblk] real partials
     uint32_t *cnt;             // [K] last-block counters

@@ -84,6 +84,43 @@ def test_block_length_does_not_change_bits_with_freezing_and_switching(precision
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_overlapped_update_equals_serial_bitwise(precision):
+    """The deferred update of a block overlaps the next block's iterations on a second stream,
+    and a seed switch waits out one block: per right-hand side the arithmetic is unchanged, so
+    the results equal the serial schedule's bit for bit (with freezing and switching)."""
+    S = _S()
+    Hc, z, B = _problem(400, 8)
+    H = S.Hamiltonian.from_csr(Hc)
+    Bt = torch.from_numpy(B).cuda()
+    runs = []
+    for serial in (False, True):
+        # seed 5 has the largest Im z: it converges first, so the seed switches
+        X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision, serial=serial,
+                                             block=8, seed_index=5)
+        assert rc == 0
+        runs.append((X.cpu().numpy(), rep["iters"].copy(), S.last_timing()["switches"]))
+    assert runs[0][2] == runs[1][2] and runs[0][2] > 0
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][0], runs[1][0])
+
+
+def test_overlapped_update_equals_serial_bitwise_window():
+    S = _S()
+    rng = np.random.default_rng(24)
+    L = 8
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    H = S.Hamiltonian.from_csr(Hc)
+    z = np.linspace(-6.5, 6.5, 12) + 1j * np.concatenate([[0.5], np.full(11, 0.04)])
+    rhs = [0, 5, 300]
+    out = []
+    for serial in (False, True):
+        G, rep, _, rc = S.greens_diag(H, z, rhs, tol=1e-10, max_iter=6000, window=3, seed_index=0, serial=serial)
+        out.append((G.cpu().numpy(), rep["iters"].copy()))
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_graph_replay_equals_direct_launches_bitwise(precision):
     """Captured HIP graphs replay exactly the kernels the direct path launches."""
     S = _S()
