@@ -70,9 +70,10 @@ typedef struct {
                                then goes to the active stored shift with the largest residual; when none is left
                                the pairs still active stop unconverged (SCOCG_ENOCONV).  0: every shift keeps
                                its full direction. */
-    int32_t serial;         /* 1: run the deferred shift update in order with the seed iterations on the caller's
-                               stream instead of overlapping it with the next block's iterations on a second
-                               stream (the results are the same bits) */
+    int32_t schedule;       /* deferred shift update: 1 in order with the seed iterations on the caller's stream;
+                               2 overlapped with the next block's iterations on a second stream; 0 automatic
+                               (overlapped when the stored directions hold at least 2^24 complex numbers, where
+                               the update outweighs the cost of the cross-stream waits).  Same bits either way. */
     int32_t reserved[2];
 } scocg_opts;
 

@@ -30,7 +30,7 @@ class Opts(ctypes.Structure):
         ("no_graph", ctypes.c_int32),
         ("refine", ctypes.c_int32),
         ("window", ctypes.c_int32),
-        ("serial", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 2),
     ]
 

@@ -23,7 +23,7 @@ def _require_gpu():
 
 def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switching=True, fixed_iter=0, block=0,
             shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False, refine=0, window=0,
-            serial=False) -> C.Opts:
+            schedule="auto") -> C.Opts:
     o = C.Opts()
     C.load().scocg_default_opts(ctypes.byref(o))
     o.tol = float(tol)
@@ -39,7 +39,7 @@ def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switc
     o.no_graph = int(bool(no_graph))
     o.refine = int(refine)
     o.window = int(window)
-    o.serial = int(bool(serial))
+    o.schedule = {"auto": 0, "serial": 1, "overlap": 2, 0: 0, 1: 1, 2: 2}[schedule]
     return o
 
 

@@ -705,7 +705,9 @@ int solve(SolveRequest &rq, hipStream_t st)
             }
         }
     } fs;
-    if (o.serial) {
+    if (o.schedule < 0 || o.schedule > 2) return fail(SCOCG_EINVAL, "schedule must be 0, 1 or 2");
+    const bool overlap = o.schedule == 2 || (o.schedule == 0 && (double)Mst * (double)ntot >= 16777216.0);
+    if (!overlap) {
         fs.sf = st;
     } else {
         HIPCHK(hipStreamCreateWithFlags(&fs.sf, hipStreamNonBlocking));

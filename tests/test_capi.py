@@ -36,7 +36,7 @@ def test_opts_struct_layout():
     C.load().scocg_default_opts(ctypes.byref(o))
     assert o.tol == 1e-8 and o.max_iter == 3000 and o.seed_index == -1 and o.seed_switching == 1
     assert ctypes.sizeof(C.Opts) == 8 + 4 * 15 + 4  # padded to 8 bytes
-    assert C.Opts.window.offset == 8 + 4 * 11 and C.Opts.serial.offset == 8 + 4 * 12
+    assert C.Opts.window.offset == 8 + 4 * 11 and C.Opts.schedule.offset == 8 + 4 * 12
     assert ctypes.sizeof(C.PairReport) == 24
 
 

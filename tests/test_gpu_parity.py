@@ -93,10 +93,10 @@ def test_overlapped_update_equals_serial_bitwise(precision):
     H = S.Hamiltonian.from_csr(Hc)
     Bt = torch.from_numpy(B).cuda()
     runs = []
-    for serial in (False, True):
+    for schedule in ("overlap", "serial"):
         # seed 5 has the largest Im z: it converges first, so the seed switches
-        X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision, serial=serial,
-                                             block=8, seed_index=5)
+        X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision,
+                                             schedule=schedule, block=8, seed_index=5)
         assert rc == 0
         runs.append((X.cpu().numpy(), rep["iters"].copy(), S.last_timing()["switches"]))
     assert runs[0][2] == runs[1][2] and runs[0][2] > 0
@@ -113,8 +113,9 @@ def test_overlapped_update_equals_serial_bitwise_window():
     z = np.linspace(-6.5, 6.5, 12) + 1j * np.concatenate([[0.5], np.full(11, 0.04)])
     rhs = [0, 5, 300]
     out = []
-    for serial in (False, True):
-        G, rep, _, rc = S.greens_diag(H, z, rhs, tol=1e-10, max_iter=6000, window=3, seed_index=0, serial=serial)
+    for schedule in ("overlap", "serial"):
+        G, rep, _, rc = S.greens_diag(H, z, rhs, tol=1e-10, max_iter=6000, window=3, seed_index=0,
+                                      schedule=schedule)
         out.append((G.cpu().numpy(), rep["iters"].copy()))
     assert np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][0], out[1][0])
