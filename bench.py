@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="default fp64 (fp32 storage for the batch workload)")
     ap.add_argument("--problems", type=int, default=8, help="lattices in the batch workload")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "overlap"],
+                    help="deferred update in order with the seed iterations, or overlapped with the next block")
     ap.add_argument("--matrix-free", action="store_true",
                     help="hubbard workload: apply H from per-species hopping tables (hubbard_upload)")
     ap.add_argument("--window", type=int, default=0,
@@ -349,7 +351,7 @@ def bench_batch(args, S, torch):
     print(f"[bench] workload batch: {len(probs)} lattices L={[p.extra['L'] for p in probs]}, {K} rhs x {M} shifts, "
           f"{prec}; directions {M * ntot * esz / 1e9:.1f} GB", file=sys.stderr, flush=True)
     opts = dict(tol=tol, max_iter=max_iter, precision=prec, block=args.block, shifts_per_wg=args.shifts_per_wg,
-                window=args.window)
+                window=args.window, schedule=args.schedule)
     S.greens_diag_batched(Hs[:1], z[:4], [rhs[0][:1]], fixed_iter=32, precision=prec, block=args.block)
     torch.cuda.synchronize()
     S.set_profiling(True)
@@ -479,7 +481,7 @@ def main():
         B = torch.from_numpy(p.rhs_dense()).to(dev)
         X = torch.empty((K, M, n), dtype=torch.complex128, device=dev)
     opts = dict(tol=p.tol, max_iter=p.max_iter, precision=args.precision, block=args.block,
-                shifts_per_wg=args.shifts_per_wg)
+                shifts_per_wg=args.shifts_per_wg, schedule=args.schedule)
     if greens:
         opts["window"] = args.window
     elif args.window:
@@ -541,7 +543,7 @@ def main():
         "config": {"workload": f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}"
                                + (f", full directions for {args.window} seed candidates" if args.window else ""),
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
-                   "block": args.block or 24, "iterations_per_step": int(np.max(iters))},
+                   "block": args.block or 24, "schedule": args.schedule, "iterations_per_step": int(np.max(iters))},
         "roofline": update_roofline(upd_ms, upd_bytes, upd_launches, args.workload),
         "hot_path": hot_path(upd_bytes, seed_iters, n, elapsed, 0 if args.matrix_free else 12 * int(p.H.nnz),
                              args.steps * int(np.max(iters))),
