@@ -342,6 +342,7 @@ extern "C" int hubbard_upload(int32_t L, int32_t n_up, int32_t n_dn, double t, d
         h.dn_hop = (const uint32_t *)(dev + o_dhop);
         h.dn_conf = (const uint32_t *)(dev + o_dcf);
         h.Dd = Dd;
+        d.hub_Dd = Dd;
         h.t = t;
         h.U = U;
         h.V = V;
@@ -567,6 +568,14 @@ int solve(SolveRequest &rq, hipStream_t st)
     for (int64_t j = 0; j + 1 < K && pairable && !rq.Hj.empty(); j += 2) pairable = rq.Hj[j] == rq.Hj[j + 1];
     s.spmv_rb = pairable ? 2 : 1;
     for (int64_t j = 0; j < K; ++j) (hdesc[j].hub ? s.has_hub : s.has_sell) = 1;
+    s.hub_lds = 1;
+    for (int64_t j = 0; j < K; ++j) {
+        const DevCSR &dj = (rq.Hj.empty() ? rq.H : rq.Hj[j])->d;
+        if (!dj.d_hub) continue;
+        // one partial per up-spin configuration must fit the nblk partial slots of the rhs
+        if (dj.hub_Dd > HUB_LDS_MAX || dj.n / dj.hub_Dd > s.nblk) s.hub_lds = 0;
+        s.hub_du_max = std::max<int64_t>(s.hub_du_max, dj.n / dj.hub_Dd);
+    }
 
     DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
         brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc, bwshift, bwslot, bUproj, bblk;

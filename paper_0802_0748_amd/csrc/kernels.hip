@@ -396,6 +396,146 @@ __device__ inline void hubbard_row(const HubbardOp *hp, int64_t row, const doubl
     up_terms(false);
 }
 
+// LDS-tiled matrix-free Hubbard product: one workgroup per (up-spin configuration iu, rhs).
+// The block p[iu, :] (the rows that share iu) is staged in LDS, so the down-spin hops read
+// LDS; the up-spin hops of iu are the same for every row of the block and read contiguous
+// stretches p[a, :].  Each row adds its terms in the stored matrix's column order (q equals
+// the stored product bit for bit); the workgroup's partial of p.q goes to slot iu, and the
+// slots past the last configuration are cleared.
+static constexpr int HUB_WG = 1024;
+
+__device__ inline double2 block_sum2_hub(double2 v, double2 *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int h = HUB_WG / 2; h > 0; h >>= 1) {
+        if (t < h) sh[t] = cadd(sh[t], sh[t + h]);
+        __syncthreads();
+    }
+    const double2 r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(HUB_WG) k_spmv_hub_lds(SolveDev s)
+{
+    __shared__ double2 pl[HUB_LDS_MAX];
+    __shared__ double2 sh2[HUB_WG];
+    const int64_t j = blockIdx.y;
+    const SeedState st = s.seed[j];
+    if (!seed_running(st, s.TB)) return;
+    const RhsDesc d = s.desc[j];
+    if (!d.hub) return;
+    const HubbardOp h = *d.hub;
+    const int64_t Dd = h.Dd;
+    const int64_t Du = d.n / Dd;
+    const int64_t iu = blockIdx.x;
+    if (iu >= Du) return;
+    // p of this rhs at row c is pv[RB * c] (RB = 2: interleaved with its partner)
+    const int RB = s.spmv_rb;
+    const double2 *pv = s.p + p_index(s, j, d, 0);
+    const int64_t r0 = iu * Dd;
+    for (int64_t c = threadIdx.x; c < Dd; c += HUB_WG) pl[c] = pv[(int64_t)RB * (r0 + c)];
+    __syncthreads();
+    const auto *up_ptr = gptr(h.up_ptr);
+    const auto *up_hop = gptr(h.up_hop);
+    const auto *dn_ptr = gptr(h.dn_ptr);
+    const auto *dn_hop = gptr(h.dn_hop);
+    const int32_t u0 = up_ptr[iu], u1 = up_ptr[iu + 1];
+    // up-spin hops to lower configurations come first in the sorted list
+    int32_t usplit = u0;
+    while (usplit < u1 && (int64_t)(up_hop[usplit] & 0x7fffffffu) < iu) ++usplit;
+    const uint32_t cu = gptr(h.up_conf)[iu];
+    auto hop_val = [&](uint32_t e) { return (e >> 31) ? h.t : -h.t; };
+    // Rows of this thread: id = threadIdx.x + i * HUB_WG.  The loops over hops run outside the
+    // loop over rows, so the independent loads of a thread's rows are in flight together;
+    // each row's own sum still takes its terms in column order.
+    constexpr int RPT = (int)((HUB_LDS_MAX + HUB_WG - 1) / HUB_WG);
+    double ax[RPT], ay[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        ax[i] = 0;
+        ay[i] = 0;
+    }
+    auto up_range = [&](int32_t k0, int32_t k1) {
+        for (int32_t k = k0; k < k1; ++k) {
+            const uint32_t e = up_hop[k];  // the same hop for every row of the block
+            const double v = hop_val(e);
+            const double2 *pa = pv + (int64_t)RB * ((int64_t)(e & 0x7fffffffu) * Dd);
+            double2 pc[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int64_t id = threadIdx.x + (int64_t)i * HUB_WG;
+                if (id < Dd) pc[i] = pa[(int64_t)RB * id];
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int64_t id = threadIdx.x + (int64_t)i * HUB_WG;
+                if (id < Dd) {
+                    ax[i] = fma(v, pc[i].x, ax[i]);
+                    ay[i] = fma(v, pc[i].y, ay[i]);
+                }
+            }
+        }
+    };
+    up_range(u0, usplit);
+    // the down-spin row of each row from LDS, with the diagonal at its place
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t id = threadIdx.x + (int64_t)i * HUB_WG;
+        if (id >= Dd) continue;
+        const uint32_t cd = gptr(h.dn_conf)[id];
+        const int on = __popc(cu & cd);
+        const int inter = __popc(cu & ring_next(cu, h.L)) + __popc(cd & ring_next(cd, h.L)) +
+                          __popc(cu & ring_next(cd, h.L)) + __popc(cd & ring_next(cu, h.L));
+        const double diag = h.U * (double)on + h.V * (double)inter;
+        const double2 pd = pl[id];
+        bool diag_done = false;
+        const int32_t d0 = dn_ptr[id], d1 = dn_ptr[id + 1];
+        for (int32_t m0 = d0; m0 < d1; m0 += HUB_CHUNK) {
+            uint32_t e[HUB_CHUNK];
+#pragma unroll
+            for (int m = 0; m < HUB_CHUNK; ++m) e[m] = (m0 + m < d1) ? dn_hop[m0 + m] : 0u;
+#pragma unroll
+            for (int m = 0; m < HUB_CHUNK; ++m) {
+                if (m0 + m < d1) {
+                    const int64_t b = e[m] & 0x7fffffffu;
+                    if (!diag_done && b > id) {
+                        ax[i] = fma(diag, pd.x, ax[i]);
+                        ay[i] = fma(diag, pd.y, ay[i]);
+                        diag_done = true;
+                    }
+                    const double2 pc = pl[b];
+                    const double v = hop_val(e[m]);
+                    ax[i] = fma(v, pc.x, ax[i]);
+                    ay[i] = fma(v, pc.y, ay[i]);
+                }
+            }
+        }
+        if (!diag_done) {
+            ax[i] = fma(diag, pd.x, ax[i]);
+            ay[i] = fma(diag, pd.y, ay[i]);
+        }
+    }
+    up_range(usplit, u1);
+    double2 pq = cmk(0, 0);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t id = threadIdx.x + (int64_t)i * HUB_WG;
+        if (id >= Dd) continue;
+        const double2 pd = pl[id];
+        const double2 qv = cfma(st.zs, pd, make_double2(-ax[i], -ay[i]));
+        s.q[d.voff + r0 + id] = qv;
+        pq = cadd(pq, cmul(pd, qv));
+    }
+    pq = block_sum2_hub(pq, sh2);
+    if (threadIdx.x == 0) {
+        s.part2[j * s.nblk + iu] = pq;
+        for (int64_t b = Du + iu; b < s.nblk; b += Du) s.part2[j * s.nblk + b] = cmk(0, 0);
+    }
+}
+
 // Slots of a slice processed per batch: the column and value loads of SPMV_CHUNK slots are
 // issued together, then their gathers, so each wave has many loads in flight.
 static constexpr int SPMV_CHUNK = 8;
@@ -1113,7 +1253,9 @@ hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
         else hipLaunchKernelGGL((k_spmv<1, false>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
     }
     if (s.has_hub) {
-        if (RB == 2) hipLaunchKernelGGL((k_spmv<2, true>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
+        if (s.hub_lds)
+            hipLaunchKernelGGL(k_spmv_hub_lds, dim3((unsigned)s.hub_du_max, (unsigned)s.K), dim3(HUB_WG), 0, st, s);
+        else if (RB == 2) hipLaunchKernelGGL((k_spmv<2, true>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
         else hipLaunchKernelGGL((k_spmv<1, true>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
     }
     hipLaunchKernelGGL(k_alpha, dim3((unsigned)s.K), dim3(WG), 0, st, s);

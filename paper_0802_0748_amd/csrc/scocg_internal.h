@@ -84,6 +84,10 @@ struct HubbardOp {
     int32_t pad;
 };
 
+// Down-spin blocks of at most this many configurations take the LDS-tiled product
+// (one 16-byte element per configuration, 64 KB of LDS).
+static constexpr int64_t HUB_LDS_MAX = 4096;
+
 // ---- device-side matrix ----
 struct DevCSR {
     int64_t n, nnz;
@@ -104,6 +108,7 @@ struct DevCSR {
     int max_w;            // widest slice
     HubbardOp *d_hub;     // matrix-free operator (device struct), or null for a stored matrix
     void *d_hub_tables;   // device tables the operator points into
+    int64_t hub_Dd;       // its down-spin configurations (host copy)
 };
 
 // ---- per right-hand side: its matrix and where its vectors live ----
@@ -162,6 +167,8 @@ struct SolveDev {
     int zper;                  // 1: one shift per rhs (M = 1, z has K entries), used by refinement
     int spmv_rb;               // right-hand sides per SpMV thread (2: each rhs pair 2i, 2i+1 shares its matrix)
     int has_sell, has_hub;     // some rhs has a stored matrix / a matrix-free Hubbard operator
+    int hub_lds;               // every Hubbard operator's down-spin block fits the LDS-tiled product
+    int64_t hub_du_max;        // largest number of up-spin configurations among them
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
 };
 

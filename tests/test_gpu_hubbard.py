@@ -3,7 +3,8 @@
 The stored matrix comes from `workloads.hubbard_ring`, an independent construction of the
 same sector (Python, numpy); the operator builds its hopping tables in the library.  Equal
 products make every solve bit for bit equal, which pins the basis order, the fermion signs
-and the diagonal of both.
+and the diagonal of both.  (Small sectors take the row-per-thread product; sectors whose
+down-spin block fits in LDS take the tiled one, whose p.q partial sums run in another order.)
 """
 
 import numpy as np
@@ -40,6 +41,37 @@ def test_operator_equals_stored_matrix_bitwise(L, nu, nd):
     Xm, _, _, _ = S.shifted_cocg_solve(Hm, z, B, fixed_iter=40, seed_index=0)
     Xo, _, _, _ = S.shifted_cocg_solve(Ho, z, B, fixed_iter=40, seed_index=0)
     assert np.array_equal(Xo.cpu().numpy(), Xm.cpu().numpy())
+
+
+@pytest.mark.parametrize("L,nu,nd", [(12, 6, 6), (11, 5, 5)])
+def test_lds_tiled_operator_matches_stored_matrix(L, nu, nd):
+    """Sectors whose down-spin block fits in LDS take the tiled product (one workgroup per
+    up-spin configuration).  Its rows equal the stored product bit for bit; only the order in
+    which p.q is summed over rows differs, so fixed-iteration solves agree to rounding and
+    tolerance-stopped ones within the residual bounds."""
+    S = _S()
+    Hc = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    Hm = S.Hamiltonian.from_csr(Hc)
+    Ho = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    z = np.linspace(-6, 12, 5) + 0.2j
+    Bn = _rhs(Hc.n, 2, L)
+    B = torch.from_numpy(Bn).cuda()
+    Xm, _, _, _ = S.shifted_cocg_solve(Hm, z, B, fixed_iter=30, seed_index=0)
+    Xo, _, _, _ = S.shifted_cocg_solve(Ho, z, B, fixed_iter=30, seed_index=0)
+    Xm, Xo = Xm.cpu().numpy(), Xo.cpu().numpy()
+    rel = np.linalg.norm(Xo - Xm, axis=2) / np.linalg.norm(Xm, axis=2)
+    assert rel.max() < 1e-10  # the FP64 parity bar; only the order of the p.q sums differs
+    tol = 1e-9
+    Xo, repo, _, rco = S.shifted_cocg_solve(Ho, z, B, tol=tol, max_iter=6000, check_true=True)
+    Xm, repm, _, rcm = S.shifted_cocg_solve(Hm, z, B, tol=tol, max_iter=6000, check_true=True)
+    assert rco == 0 and rcm == 0
+    assert repo["res_true"].max() < 20 * tol
+    # freeze iterations are rounding-sensitive decisions (and a switch moves them all), so
+    # the two solves are compared through the residual bounds, not iteration by iteration
+    assert np.abs(repo["iters"] - repm["iters"]).max() <= 0.1 * repm["iters"].max() + 2
+    bound = (repo["res_true"] + repm["res_true"]) / z.imag[None, :]
+    diff = np.linalg.norm(Xo.cpu().numpy() - Xm.cpu().numpy(), axis=2)
+    assert np.all(diff <= bound * (1 + 1e-6))
 
 
 def test_operator_production_solve_matches_stored_matrix_and_oracle():
