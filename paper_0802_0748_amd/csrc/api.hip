@@ -568,6 +568,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     for (int64_t j = 0; j + 1 < K && pairable && !rq.Hj.empty(); j += 2) pairable = rq.Hj[j] == rq.Hj[j + 1];
     s.spmv_rb = pairable ? 2 : 1;
     for (int64_t j = 0; j < K; ++j) (hdesc[j].hub ? s.has_hub : s.has_sell) = 1;
+    for (int64_t j = 0; j < K; ++j) (hdesc[j].n >= RED_BIG_ROWS ? s.has_red_big : s.has_red_small) = 1;
     s.hub_lds = 1;
     for (int64_t j = 0; j < K; ++j) {
         const DevCSR &dj = (rq.Hj.empty() ? rq.H : rq.Hj[j])->d;

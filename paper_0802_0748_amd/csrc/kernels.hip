@@ -18,12 +18,15 @@ namespace scocg {
 // ---------------------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------------------
+// Tree sums over the NT threads of a workgroup (sh holds NT entries); the result is in
+// every thread.
+template <int NT = WG>
 __device__ inline double2 block_sum2(double2 v, double2 *sh)
 {
     int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s) sh[t] = cadd(sh[t], sh[t + s]);
         __syncthreads();
     }
@@ -32,12 +35,13 @@ __device__ inline double2 block_sum2(double2 v, double2 *sh)
     return r;
 }
 
+template <int NT = WG>
 __device__ inline double block_sum1(double v, double *sh)
 {
     int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s) sh[t] += sh[t + s];
         __syncthreads();
     }
@@ -69,30 +73,29 @@ __device__ inline bool arrive_last(uint32_t *cnt, int64_t j, uint32_t nblk)
     return last;
 }
 
-// Fixed-order sum of nblk complex partials (every thread participates, result in all threads):
-// thread t adds partials t, t + WG, t + 2 WG, ... in order, then the threads' sums are added
-// as a tree.  COHERENT: the partials were written by other workgroups of the same launch
+// Fixed-order sum of nblk complex partials by NT threads (result in all threads): thread t
+// adds partials t, t + NT, t + 2 NT, ... in order, then the threads' sums are added as a tree.  COHERENT: the partials were written by other workgroups of the same launch
 // (read past the caches with atomic loads); otherwise by an earlier launch (plain loads, which
 // the compiler can issue many at a time).
 // With plain loads a thread fetches 32 of its partials at a time (the sum order is unchanged),
 // so a row count with tens of thousands of partials is not bound by one load's latency each.
 static constexpr int SUM_BATCH = 32;
 
-template <bool COHERENT>
+template <bool COHERENT, int NT = WG>
 __device__ inline double2 sum_partials2(const double2 *part, int64_t nblk, double2 *sh)
 {
     double2 acc = cmk(0, 0);
     int64_t b = threadIdx.x;
     if (!COHERENT) {
-        for (; b + (SUM_BATCH - 1) * WG < nblk; b += SUM_BATCH * WG) {
+        for (; b + (SUM_BATCH - 1) * NT < nblk; b += SUM_BATCH * NT) {
             double2 v[SUM_BATCH];
 #pragma unroll
-            for (int u = 0; u < SUM_BATCH; ++u) v[u] = part[b + u * WG];
+            for (int u = 0; u < SUM_BATCH; ++u) v[u] = part[b + u * NT];
 #pragma unroll
             for (int u = 0; u < SUM_BATCH; ++u) acc = cadd(acc, v[u]);
         }
     }
-    for (; b < nblk; b += WG) {
+    for (; b < nblk; b += NT) {
         if (COHERENT) {
             const double *pp = (const double *)(part + b);
             acc = cadd(acc, cmk(load_coherent(pp), load_coherent(pp + 1)));
@@ -100,26 +103,34 @@ __device__ inline double2 sum_partials2(const double2 *part, int64_t nblk, doubl
             acc = cadd(acc, part[b]);
         }
     }
-    return block_sum2(acc, sh);
+    return block_sum2<NT>(acc, sh);
 }
 
-template <bool COHERENT>
+template <bool COHERENT, int NT = WG>
 __device__ inline double sum_partials1(const double *part, int64_t nblk, double *sh)
 {
     double acc = 0;
     int64_t b = threadIdx.x;
     if (!COHERENT) {
-        for (; b + (SUM_BATCH - 1) * WG < nblk; b += SUM_BATCH * WG) {
+        for (; b + (SUM_BATCH - 1) * NT < nblk; b += SUM_BATCH * NT) {
             double v[SUM_BATCH];
 #pragma unroll
-            for (int u = 0; u < SUM_BATCH; ++u) v[u] = part[b + u * WG];
+            for (int u = 0; u < SUM_BATCH; ++u) v[u] = part[b + u * NT];
 #pragma unroll
             for (int u = 0; u < SUM_BATCH; ++u) acc += v[u];
         }
     }
-    for (; b < nblk; b += WG) acc += COHERENT ? load_coherent(part + b) : part[b];
-    return block_sum1(acc, sh);
+    for (; b < nblk; b += NT) acc += COHERENT ? load_coherent(part + b) : part[b];
+    return block_sum1<NT>(acc, sh);
 }
+
+// The per-rhs reductions of the seed iteration (alpha, beta) run with WG threads, or with
+// RWG_BIG threads for a right-hand side of at least RED_BIG_ROWS rows (a Hubbard sector of ten
+// million rows leaves tens of thousands of partials).  The choice depends on the rhs's own
+// row count only, so a right-hand side sums in the same order alone or in any batch.
+static constexpr int RWG_BIG = 1024;
+
+__device__ inline bool red_big(const RhsDesc &d) { return d.n >= RED_BIG_ROWS; }
 
 __device__ inline void reset_counter(uint32_t *cnt, int64_t j)
 {
@@ -404,20 +415,6 @@ __device__ inline void hubbard_row(const HubbardOp *hp, int64_t row, const doubl
 // slots past the last configuration are cleared.
 static constexpr int HUB_WG = 1024;
 
-__device__ inline double2 block_sum2_hub(double2 v, double2 *sh)
-{
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int h = HUB_WG / 2; h > 0; h >>= 1) {
-        if (t < h) sh[t] = cadd(sh[t], sh[t + h]);
-        __syncthreads();
-    }
-    const double2 r = sh[0];
-    __syncthreads();
-    return r;
-}
-
 __global__ void __launch_bounds__(HUB_WG) k_spmv_hub_lds(SolveDev s)
 {
     __shared__ double2 pl[HUB_LDS_MAX];
@@ -529,7 +526,7 @@ __global__ void __launch_bounds__(HUB_WG) k_spmv_hub_lds(SolveDev s)
         s.q[d.voff + r0 + id] = qv;
         pq = cadd(pq, cmul(pd, qv));
     }
-    pq = block_sum2_hub(pq, sh2);
+    pq = block_sum2<HUB_WG>(pq, sh2);
     if (threadIdx.x == 0) {
         s.part2[j * s.nblk + iu] = pq;
         for (int64_t b = Du + iu; b < s.nblk; b += Du) s.part2[j * s.nblk + b] = cmk(0, 0);
@@ -638,13 +635,15 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
     }
 }
 
-__global__ void __launch_bounds__(WG) k_alpha(SolveDev s)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_alpha(SolveDev s)
 {
-    __shared__ double2 sh2[WG];
+    __shared__ double2 sh2[NT];
     const int64_t j = blockIdx.x;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
-    const double2 tot = sum_partials2<false>(s.part2 + j * s.nblk, s.nblk, sh2);
+    if (red_big(s.desc[j]) != (NT == RWG_BIG)) return;
+    const double2 tot = sum_partials2<false, NT>(s.part2 + j * s.nblk, s.nblk, sh2);
     if (threadIdx.x == 0) {
         if (cis0(tot) || cis0(st.rho)) s.seed[j].status = SEED_BREAKDOWN;
         else s.ahist[j * s.TB + st.step] = cdiv(st.rho, tot);
@@ -681,15 +680,17 @@ __global__ void __launch_bounds__(WG) k_rupd(SolveDev s)
     }
 }
 
-__global__ void __launch_bounds__(WG) k_beta(SolveDev s)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_beta(SolveDev s)
 {
-    __shared__ double2 sh2[WG];
-    __shared__ double sh1[WG];
+    __shared__ double2 sh2[NT];
+    __shared__ double sh1[NT];
     const int64_t j = blockIdx.x;
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
-    const double2 rho_new = sum_partials2<false>(s.part2 + j * s.nblk, s.nblk, sh2);
-    const double rnorm = sqrt(sum_partials1<false>(s.part1 + j * s.nblk, s.nblk, sh1));
+    if (red_big(s.desc[j]) != (NT == RWG_BIG)) return;
+    const double2 rho_new = sum_partials2<false, NT>(s.part2 + j * s.nblk, s.nblk, sh2);
+    const double rnorm = sqrt(sum_partials1<false, NT>(s.part1 + j * s.nblk, s.nblk, sh1));
     if (threadIdx.x == 0) {
         const double2 a = s.ahist[j * s.TB + st.step];
         const double2 beta = cdiv(rho_new, st.rho);
@@ -1258,9 +1259,11 @@ hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
         else if (RB == 2) hipLaunchKernelGGL((k_spmv<2, true>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
         else hipLaunchKernelGGL((k_spmv<1, true>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
     }
-    hipLaunchKernelGGL(k_alpha, dim3((unsigned)s.K), dim3(WG), 0, st, s);
+    if (s.has_red_small) hipLaunchKernelGGL(k_alpha<WG>, dim3((unsigned)s.K), dim3(WG), 0, st, s);
+    if (s.has_red_big) hipLaunchKernelGGL(k_alpha<RWG_BIG>, dim3((unsigned)s.K), dim3(RWG_BIG), 0, st, s);
     hipLaunchKernelGGL(k_rupd, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
-    hipLaunchKernelGGL(k_beta, dim3((unsigned)s.K), dim3(WG), 0, st, s);
+    if (s.has_red_small) hipLaunchKernelGGL(k_beta<WG>, dim3((unsigned)s.K), dim3(WG), 0, st, s);
+    if (s.has_red_big) hipLaunchKernelGGL(k_beta<RWG_BIG>, dim3((unsigned)s.K), dim3(RWG_BIG), 0, st, s);
     return hipGetLastError();
 }
 

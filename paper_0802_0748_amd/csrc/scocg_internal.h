@@ -84,6 +84,9 @@ struct HubbardOp {
     int32_t pad;
 };
 
+// Right-hand sides of at least this many rows sum their seed reductions with 1024 threads.
+static constexpr int64_t RED_BIG_ROWS = 1 << 21;
+
 // Down-spin blocks of at most this many configurations take the LDS-tiled product
 // (one 16-byte element per configuration, 64 KB of LDS).
 static constexpr int64_t HUB_LDS_MAX = 4096;
@@ -168,6 +171,7 @@ struct SolveDev {
     int spmv_rb;               // right-hand sides per SpMV thread (2: each rhs pair 2i, 2i+1 shares its matrix)
     int has_sell, has_hub;     // some rhs has a stored matrix / a matrix-free Hubbard operator
     int hub_lds;               // every Hubbard operator's down-spin block fits the LDS-tiled product
+    int has_red_small, has_red_big; // some rhs below / at or above 2^21 rows (per-rhs reduction width)
     int64_t hub_du_max;        // largest number of up-spin configurations among them
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
 };
