@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
+FP32_PEAK_TFS = 157.3  # MI355X FP32 vector (packed)
 METRIC = "shift\u00d7RHS solves/sec to rel. residual 1e-8; SpMV achieved HBM GB/s vs peak"
 UPDATE_KERNEL_SOURCES = ["flush.hip", "device_common.h", "scocg_internal.h"]
 
@@ -248,8 +250,10 @@ def trace_summary(args):
         lines += ["", f"Deferred update `{name.split('(')[0].replace('void ', '')}`: rocprofv3 average "
                       f"{avg_ms:.3f} ms per launch over the {len(disp)} launches of the benchmark solves; "
                       f"bench.py's HIP-event average over the same solves: {line['roofline']['avg_launch_ms']:.3f} ms "
-                      f"({line['roofline']['bytes_per_launch'] / 1e9:.2f} GB algorithmic per launch, "
-                      f"{line['roofline']['achieved']:.0f} GB/s)."]
+                      f"({line['roofline']['bytes_per_launch'] / 1e9:.2f} GB and "
+                      f"{line['roofline'].get('flops_per_launch', 0) / 1e9:.0f} GFLOP algorithmic per launch: "
+                      f"{line['roofline']['achieved']:.1f} {line['roofline']['unit']}, "
+                      f"{100 * line['roofline']['frac']:.1f} % of the {line['roofline']['bound']} peak)."]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(f"[bench] wrote {out}", file=sys.stderr)
@@ -311,13 +315,27 @@ def load_workload(args):
     return p, desc
 
 
-def update_roofline(upd_ms, upd_bytes, upd_launches, workload):
-    achieved = (upd_bytes / 1e9) / (upd_ms / 1e3) if upd_ms > 0 else 0.0
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload),
-            "kernel": "k_flush (deferred per-shift update)",
-            "avg_launch_ms": upd_ms / max(upd_launches, 1),
-            "bytes_per_launch": upd_bytes / max(upd_launches, 1)}
+def update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, workload, precision):
+    """Roofline of the deferred per-shift update from its device-counted algorithmic bytes and
+    flops over its summed launch time.  Its arithmetic intensity is about T * 16 flops per 64 B
+    of x_k, u_k (FP64, T steps per block); above the machine balance (FP64 vector peak over
+    HBM peak, 9.8 flop/B; FP32 storage: 19.7) the kernel is bound by its fused multiply-adds
+    and is reported against the vector peak, below it against HBM."""
+    t = upd_ms / 1e3
+    gbs = (upd_bytes / 1e9) / t if t > 0 else 0.0
+    tfs = (upd_flops / 1e12) / t if t > 0 else 0.0
+    alu_peak = FP64_PEAK_TFS if precision == "fp64" else FP32_PEAK_TFS
+    intensity = upd_flops / upd_bytes if upd_bytes > 0 else 0.0
+    per = {"kernel": "k_flush (deferred per-shift update)", "avg_launch_ms": upd_ms / max(upd_launches, 1),
+           "bytes_per_launch": upd_bytes / max(upd_launches, 1), "flops_per_launch": upd_flops / max(upd_launches, 1),
+           "intensity_flop_per_byte": intensity, "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+           "alu_achieved_tflops": tfs, "alu_frac": tfs / alu_peak}
+    traffic = measured_traffic(workload)
+    if intensity > alu_peak * 1e3 / HBM_PEAK_GBS:
+        return {"bound": "alu", "achieved": tfs, "peak": alu_peak, "unit": "TFLOP/s", "frac": tfs / alu_peak,
+                "traffic": traffic, **per}
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": traffic, **per}
 
 
 def hot_path(update_bytes, seed_iterations, n, elapsed, matrix_bytes=0, sweeps=0):
@@ -356,7 +374,7 @@ def bench_batch(args, S, torch):
     S.greens_diag_batched(Hs[:1], z[:4], [rhs[0][:1]], fixed_iter=32, precision=prec, block=args.block)
     torch.cuda.synchronize()
     S.set_profiling(True)
-    upd_ms = upd_bytes = 0.0
+    upd_ms = upd_bytes = upd_flops = 0.0
     upd_launches = converged = 0
     iters = None
     t0 = time.perf_counter()
@@ -371,6 +389,7 @@ def bench_batch(args, S, torch):
             t = S.last_timing()
             upd_ms += t["update_ms"]
             upd_bytes += t["update_bytes"]
+            upd_flops += t["update_flops"]
             upd_launches += t["update_launches"]
             status_l += [r["status"] for r in reps]
             iters_l += [r["iters"] for r in reps]
@@ -399,9 +418,9 @@ def bench_batch(args, S, torch):
                                 + (f", full directions for {args.window} seed candidates per rhs" if args.window
                                    else "")),
                    "n": int(sum(p.H.n for p in probs)), "nnz": int(sum(p.H.nnz for p in probs)), "n_shift": M,
-                   "n_rhs": K, "precision": prec, "block": args.block or 24,
+                   "n_rhs": K, "precision": prec, "block": args.block or 48,
                    "iterations_per_step": int(np.max(iters))},
-        "roofline": update_roofline(upd_ms, upd_bytes, upd_launches, "batch"),
+        "roofline": update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, "batch", prec),
     }
     if not args.no_cpu_baseline:
         p0 = probs[0]
@@ -434,11 +453,11 @@ def run_variants(S, torch, n_rhs):
 
     Xb, t_b = timed(lambda: S.shifted_cocg_solve(H, p.z, B, **base)[0])
     ref = Xb.cpu().numpy()
-    out["batched fp64, block 24"] = (t_b, 0.0)
+    out["batched fp64, block 48"] = (t_b, 0.0)
     forms = [("one rhs at a time, fp64, update every iteration (plain)", dict(block=1), 1),
-             ("one rhs at a time, fp64, block 24", dict(block=24), 1),
-             ("batched fp32 storage, block 24", dict(block=24, precision="fp32"), K),
-             ("batched fp32 storage + fp64 refinement", dict(block=24, precision="fp32", refine=2), K)]
+             ("one rhs at a time, fp64, block 48", dict(block=48), 1),
+             ("batched fp32 storage, block 48", dict(block=48, precision="fp32"), K),
+             ("batched fp32 storage + fp64 refinement", dict(block=48, precision="fp32", refine=2), K)]
     for name, extra, per in forms:
         X = np.zeros_like(ref)
         t = 0.0
@@ -517,7 +536,7 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s rc={rc}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    upd_ms = upd_bytes = 0.0
+    upd_ms = upd_bytes = upd_flops = 0.0
     upd_launches = seed_iters = 0
     converged = 0
     iters = None
@@ -528,6 +547,7 @@ def main():
         t = S.last_timing()
         upd_ms += t["update_ms"]
         upd_bytes += t["update_bytes"]
+        upd_flops += t["update_flops"]
         upd_launches += t["update_launches"]
         seed_iters += t["iterations"]
         converged += int((rep["status"] == 0).sum())
@@ -555,8 +575,8 @@ def main():
         "config": {"workload": f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}"
                                + (f", full directions for {args.window} seed candidates" if args.window else ""),
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
-                   "block": args.block or 24, "schedule": args.schedule, "iterations_per_step": int(np.max(iters))},
-        "roofline": update_roofline(upd_ms, upd_bytes, upd_launches, args.workload),
+                   "block": args.block or 48, "schedule": args.schedule, "iterations_per_step": int(np.max(iters))},
+        "roofline": update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, args.workload, args.precision),
         "hot_path": hot_path(upd_bytes, seed_iters, n, elapsed, 0 if args.matrix_free else 12 * int(p.H.nnz),
                              args.steps * int(np.max(iters))),
     }

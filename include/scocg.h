@@ -55,8 +55,9 @@ typedef struct {
     int32_t seed_index;     /* initial seed shift; -1: smallest Im z, then Re z nearest Tr(H)/n, then lowest index */
     int32_t seed_switching; /* 1: switch seed when it converges (Sec. 3.3) */
     int32_t fixed_iter;     /* > 0: run exactly this many iterations, no freezing, no switching */
-    int32_t block;          /* iterations per deferred shift update (1,2,4,8,16,24,32); 0 = automatic (24) */
-    int32_t shifts_per_wg;  /* shifts one workgroup updates in the deferred update; 0 = automatic */
+    int32_t block;          /* iterations per deferred shift update (1,2,4,8,16,24,32,40,48); 0 = automatic (48) */
+    int32_t shifts_per_wg;  /* shifts one workgroup updates in the deferred update (1 .. 64); 0 = automatic
+                               (all shifts up to 64) */
     int32_t check_true;     /* 1: compute the FP64 true residual of every pair into the report */
     int32_t keep_tape;      /* 1: keep the solutions for backward() */
     int32_t no_graph;       /* 1: launch every kernel directly instead of replaying captured HIP graphs */
@@ -218,7 +219,7 @@ const char *scocg_last_error(void);
 /*
  * Timing of the most recent solve on this thread, from HIP events on its stream:
  * the summed duration and launch count of the deferred shift-update kernel and
- * of the seed kernels, and the algorithmic bytes the shift update moved.
+ * of the seed kernels, and the algorithmic bytes and flops of the shift update.
  */
 typedef struct {
     double update_ms;       /* total time in the deferred per-shift update kernel */
@@ -228,6 +229,8 @@ typedef struct {
     int64_t iterations;     /* seed iterations summed over right-hand sides */
     int64_t blocks;         /* blocks of iterations */
     int64_t switches;       /* seed switches */
+    double update_flops;    /* algorithmic flops of the update launches: per pair and step it takes, two complex
+                               multiply-adds (16 flops) per row, one (8) where only the direction is stored */
 } scocg_timing;
 int scocg_last_timing(scocg_timing *t);
 /* 1: record per-launch events around the update kernel (adds a small overhead). */

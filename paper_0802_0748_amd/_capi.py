@@ -53,6 +53,7 @@ class Timing(ctypes.Structure):
         ("iterations", ctypes.c_int64),
         ("blocks", ctypes.c_int64),
         ("switches", ctypes.c_int64),
+        ("update_flops", ctypes.c_double),
     ]
 
 

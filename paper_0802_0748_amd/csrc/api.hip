@@ -481,13 +481,15 @@ int solve(SolveRequest &rq, hipStream_t st)
     for (int64_t k = 0; k < nz; ++k)
         if (!std::isfinite(rq.z[2 * k]) || !std::isfinite(rq.z[2 * k + 1]))
             return fail(SCOCG_EINVAL, "non-finite shift");
-    // 24 iterations per deferred update: the update streams x_k, u_k at copy bandwidth and
-    // its arithmetic (8 fused multiply-adds per step) still hides under the memory time;
-    // longer blocks hold the residual history in so many registers that occupancy drops
-    int TB = o.block > 0 ? o.block : 24;
-    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16 && TB != 24 && TB != 32)
-        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8, 16, 24 or 32");
-    int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 32);
+    // 48 iterations per deferred update: x_k, u_k are read and written once per block, so
+    // the update's bytes per iteration fall as 1/T; at T = 48 its arithmetic (8 fused
+    // multiply-adds per step) still fits under the memory time of an FP64 pair, and the
+    // residual history (T * 1 KiB per 64-row tile in LDS) leaves three workgroups per CU
+    int TB = o.block > 0 ? o.block : 48;
+    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16 && TB != 24 && TB != 32 && TB != 40 && TB != 48)
+        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8, 16, 24, 32, 40 or 48");
+    if (o.shifts_per_wg > 64) return fail(SCOCG_EINVAL, "shifts_per_wg must be at most 64");
+    int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 64);
     std::vector<int32_t> seeds(K, 0);
     for (int64_t j = 0; j < K; ++j) {
         if (rq.zper) {
@@ -626,7 +628,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     ALLOC(bp1, K * s.nblk * sizeof(double));
     ALLOC(bcnt, K * sizeof(uint32_t));
     ALLOC(bsd, K * sizeof(int32_t));
-    ALLOC(bstats, 2 * sizeof(unsigned long long));
+    ALLOC(bstats, 3 * sizeof(unsigned long long));
     if (rq.unit_idx) ALLOC(bidx, K * sizeof(int64_t));
 
     s.z = bz.as<double2>();
@@ -677,7 +679,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     HIPCHK(launch_zero(bcnt.ptr, K * sizeof(uint32_t), st));
     HIPCHK(launch_zero(bnact.ptr, 2 * KM * sizeof(int32_t), st));
     HIPCHK(launch_zero(bblk.ptr, 2 * (size_t)K * 4 * sizeof(int32_t), st));
-    HIPCHK(launch_zero(bstats.ptr, 2 * sizeof(unsigned long long), st));
+    HIPCHK(launch_zero(bstats.ptr, 3 * sizeof(unsigned long long), st));
     if (need_full) HIPCHK(launch_zero(s.X, (size_t)M * ntot * esz, st));
     HIPCHK(launch_zero(s.p, 2 * vec * sizeof(double2), st));
     HIPCHK(launch_init(s, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, bsd.as<int32_t>(), limit, st));
@@ -855,10 +857,11 @@ int solve(SolveRequest &rq, hipStream_t st)
     HIPCHK(hipMemcpyAsync(h_it.data(), s.iters, KM * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_st.data(), s.pstatus, KM * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_res.data(), s.res, KM * sizeof(double), hipMemcpyDeviceToHost, st));
-    unsigned long long h_stats[2] = {0, 0};
+    unsigned long long h_stats[3] = {0, 0, 0};
     HIPCHK(hipMemcpyAsync(h_stats, s.stats, sizeof(h_stats), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     g_timing.update_bytes = (double)h_stats[0];
+    g_timing.update_flops = (double)h_stats[2];
     float tot_ms = 0;
     HIPCHK(hipEventElapsedTime(&tot_ms, ev_t0, ev_t1));
     g_timing.total_ms = tot_ms;

@@ -159,6 +159,189 @@ __global__ void __launch_bounds__(WG) k_flush(const int32_t *__restrict__ blk, c
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Long blocks (T >= 24).  The T residuals of a 64-row tile are staged once in LDS and shared
+// by the FL_W waves of the workgroup; each wave takes every FL_W-th active slot of the shift
+// group (ranked from a ballot of the group's activity, so no loads steer the loop), keeps
+// x_k and u_k in registers and fetches the next pair's while it computes.  The coefficients
+// are read with scalar loads in chunks of C steps: at each chunk boundary one wait covers
+// the chunk's coefficients and residuals, then the next chunk's loads are issued and the
+// chunk is computed while they are in flight.  (Left to itself the compiler waits for them
+// two steps at a time, which exposes the L2 latency of every coefficient line; that, not
+// register pressure, is what stops the register form above beyond T = 24.)  Every pair gets
+// the steps of k_flush in the same order, so the results are the same bits.
+// ---------------------------------------------------------------------------------------
+constexpr int FL_W = 8;  // waves per workgroup of the long-block update
+
+// s_waitcnt lgkmcnt(0) (gfx9 encoding, vmcnt and expcnt left at their maxima), fenced so
+// that neither the compiler's code motion (empty asm with a memory clobber) nor the machine
+// scheduler (scheduling barriers) moves loads or arithmetic across it
+#define FLUSH_CHUNK_WAIT()                     \
+    do {                                       \
+        asm volatile("" ::: "memory");         \
+        __builtin_amdgcn_sched_barrier(0);     \
+        __builtin_amdgcn_s_waitcnt(0xC07F);    \
+        __builtin_amdgcn_sched_barrier(0);     \
+        asm volatile("" ::: "memory");         \
+    } while (0)
+
+// TB steps of one pair: cf is the pair's (a', b') table, lrow the thread's column of the
+// LDS history (stride 64); WX = false leaves x alone (projection mode away from the kept row)
+template <int TB, int C, typename V, bool WX>
+__device__ inline void flush_pair_steps(const V *__restrict__ cf, const V *lrow, V &x, V &u)
+{
+    constexpr int NC = TB / C;
+    V ca[2][C], cb[2][C], rr[2][C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        if (WX) ca[0][t] = cf[2 * t];
+        cb[0][t] = cf[2 * t + 1];
+        rr[0][t] = lrow[t * 64];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        FLUSH_CHUNK_WAIT();
+        if (c + 1 < NC) {
+#pragma unroll
+            for (int t = 0; t < C; ++t) {
+                const int s = (c + 1) * C + t;
+                if (WX) ca[(c + 1) & 1][t] = cf[2 * s];
+                cb[(c + 1) & 1][t] = cf[2 * s + 1];
+                rr[(c + 1) & 1][t] = lrow[s * 64];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            u = cfma(cb[c & 1][t], u, rr[c & 1][t]);
+            if (WX) x = cfma(ca[c & 1][t], u, x);
+        }
+        // the chunk's arithmetic stays ahead of the next boundary
+        asm volatile("" : "+v"(u.x), "+v"(u.y), "+v"(x.x), "+v"(x.y));
+    }
+}
+
+template <int TB, int C, typename V, bool PROJ>
+__global__ void __launch_bounds__(64 * FL_W)
+    k_flush_lds(const int32_t *__restrict__ blk, const double2 *__restrict__ ring, const V *__restrict__ coef,
+                const int32_t *__restrict__ nact, V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
+                const int64_t *__restrict__ proj_row, const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
+                int ngroups, const int32_t *__restrict__ wshift, int64_t Mst, int R)
+{
+    static_assert(TB % C == 0, "the block length must be a whole number of chunks");
+    const int64_t j = blockIdx.y / ngroups;
+    const int g = blockIdx.y % ngroups;
+    const int ns = blk[4 * j + 0];
+    if (ns == 0) return;
+    const int base = blk[4 * j + 1];
+    const bool fresh = blk[4 * j + 2] != 0;
+    const int64_t n = desc[j].n;
+    const int64_t voff = desc[j].voff;
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    if (row0 >= n) return;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int lane = threadIdx.x % 64;
+    const int64_t row = row0 + lane;
+    const bool valid = row < n;
+    const int64_t rowc = valid ? row : n - 1;
+    // slots k0 .. k1-1 (at most 64); slot s holds shift kof(s)
+    const int64_t k0 = (int64_t)g * G;
+    const int64_t k1 = min(k0 + G, Mst);
+    auto kof = [&](int64_t s) -> int64_t { return (PROJ && wshift) ? (int64_t)wshift[j * Mst + s] : s; };
+    const bool act = lane < k1 - k0 && nact[j * M + kof(k0 + lane)] > 0;
+    const uint64_t mask = __ballot(act);
+    if (mask == 0) return;  // frozen group: leave before reading the history
+    __shared__ V lr[TB * 64];
+    for (int t = w; t < TB; t += FL_W)
+        lr[t * 64 + lane] = (t < ns && valid) ? to_v<V>(ring[(int64_t)((base + t) % R) * ntot + voff + row])
+                                              : to_v<V>(cmk(0, 0));
+    __syncthreads();
+    uint64_t mine = 0;  // this wave's slots: every FL_W-th active one, from rank w
+    {
+        int rank = 0;
+        for (uint64_t m = mask; m; m &= m - 1, ++rank)
+            if (rank % FL_W == w) mine |= m & (~m + 1);
+    }
+    if (mine == 0) return;
+    if constexpr (!PROJ) X += M * voff;
+    P += Mst * voff;
+    const int64_t prow = PROJ ? proj_row[j] : -1;
+    // projection mode needs x_k only in the workgroup that holds the kept row (uniform test)
+    const bool with_x = !PROJ || (prow >= row0 && prow < row0 + 64);
+    // an opaque base keeps the compiler from hoisting the history reads out of the pair loop
+    int lo = lane;
+    asm volatile("" : "+v"(lo));
+    const V *lrow = lr + lo;
+    auto take = [&]() -> int64_t {
+        const int b = __builtin_ctzll(mine);
+        mine &= mine - 1;
+        return k0 + b;
+    };
+    auto fetch = [&](int64_t s, V &x, V &u) {
+        x = to_v<V>(cmk(0, 0));
+        u = x;
+        if (fresh) return;
+        u = ld_nt(P + s * n + rowc);
+        if constexpr (PROJ) {
+            if (row == prow) x = to_v<V>(Xproj[j * M + kof(s)]);
+        } else {
+            x = ld_nt(X + s * n + rowc);
+        }
+    };
+    int64_t sn = take();
+    V xn, un;
+    fetch(sn, xn, un);
+    while (true) {
+        const int64_t s = sn;
+        V x = xn, u = un;
+        const bool more = mine != 0;
+        if (more) {
+            sn = take();
+            fetch(sn, xn, un);
+        }
+        const int64_t pair = j * M + kof(s);
+        const V *cf = coef + pair * TB * 2;
+        if (with_x) flush_pair_steps<TB, C, V, true>(cf, lrow, x, u);
+        else flush_pair_steps<TB, C, V, false>(cf, lrow, x, u);
+        if (valid) {
+            st_nt(P + s * n + row, u);
+            if constexpr (PROJ) {
+                if (row == prow) Xproj[pair] = make_double2((double)x.x, (double)x.y);
+            } else {
+                st_nt(X + s * n + row, x);
+            }
+        }
+        if (!more) break;
+    }
+}
+
+template <int TB, int C, typename V>
+static hipError_t flush_lds(const SolveDev &s, hipStream_t st)
+{
+    const int G = s.shifts_per_wg;
+    if (G < 1 || G > 64) return hipErrorInvalidConfiguration;
+    const int ng = (int)((s.Mst + G - 1) / G);
+    if (s.K * ng > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const dim3 g((unsigned)(s.nblk * (WG / 64)), (unsigned)(s.K * ng));
+    const V *coef = (const V *)s.coef;
+    if (s.Xproj)
+        hipLaunchKernelGGL((k_flush_lds<TB, C, V, true>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
+                           (V *)nullptr, (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst,
+                           s.R);
+    else
+        hipLaunchKernelGGL((k_flush_lds<TB, C, V, false>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
+                           (V *)s.X, (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng,
+                           (const int32_t *)nullptr, s.M, s.R);
+    return hipGetLastError();
+}
+
+template <int TB, int C>
+static hipError_t flush_tb_lds(const SolveDev &s, hipStream_t st)
+{
+    if (s.precision == 0) return flush_lds<TB, C, double2>(s, st);
+    return flush_lds<TB, C, float2>(s, st);
+}
+
 template <int TB, typename V, int NP>
 static hipError_t flush_v(const SolveDev &s, hipStream_t st)
 {
@@ -177,8 +360,8 @@ static hipError_t flush_v(const SolveDev &s, hipStream_t st)
     return hipGetLastError();
 }
 
-// Pairs in flight per thread: the residual history takes 4 (FP64) or 2 (FP32) registers per
-// step, so long blocks keep fewer pairs in flight to hold the occupancy.
+// Short blocks (T <= 16): the residual history in registers, pairs in flight per thread by
+// its size (4 registers per step in FP64, 2 in FP32).
 template <int TB>
 static hipError_t flush_tb(const SolveDev &s, hipStream_t st)
 {
@@ -194,8 +377,11 @@ hipError_t launch_flush(const SolveDev &s, hipStream_t st)
     case 4: return flush_tb<4>(s, st);
     case 8: return flush_tb<8>(s, st);
     case 16: return flush_tb<16>(s, st);
-    case 24: return flush_tb<24>(s, st);
-    case 32: return flush_tb<32>(s, st);
+    // long blocks: chunks of C steps with C * 8 scalar registers per coefficient buffer
+    case 24: return flush_tb_lds<24, 6>(s, st);
+    case 32: return flush_tb_lds<32, 4>(s, st);
+    case 40: return flush_tb_lds<40, 5>(s, st);
+    case 48: return flush_tb_lds<48, 6>(s, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -723,8 +723,9 @@ __global__ void __launch_bounds__(NT) k_beta(SolveDev s)
 // writes (a'_n, b'_n) for every step of the block in which the pair is still active.
 // ---------------------------------------------------------------------------------------
 template <typename V>
-__device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t pair)
+__device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t pair, unsigned long long &flops)
 {
+    flops = 0ull;
     const int64_t j = pair / s.M, k = pair % s.M;
     const SeedState st = s.seed[j];
     const int ns = st.step;
@@ -801,13 +802,16 @@ __device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t
     const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;
     const unsigned long long nv = s.X ? 2ull : 1ull;
     const unsigned long long rw = (st.iter - ns == 0) ? 1ull : 2ull;
+    // algorithmic flops: the pair's own steps (not the padding), two complex multiply-adds
+    // (16 flops) per row and step, one (8) where only u_k is stored
+    flops = (unsigned long long)na * 8ull * nv * (unsigned long long)s.desc[j].n;
     return nv * rw * esz * (unsigned long long)s.desc[j].n;
 }
 
 template <typename V>
 __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
 {
-    __shared__ unsigned long long shb[WG];
+    __shared__ unsigned long long shb[WG], shf[WG];
     __shared__ unsigned int shc[WG];
     const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (pair < s.K * s.M && pair % s.M == 0) {
@@ -818,13 +822,16 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
         s.blk[4 * j + 1] = st.base;
         s.blk[4 * j + 2] = st.iter == st.step ? 1 : 0;
     }
-    const unsigned long long b = pair < s.K * s.M ? pair_scalars_one<V>(s, pair) : 0ull;
+    unsigned long long f = 0ull;
+    const unsigned long long b = pair < s.K * s.M ? pair_scalars_one<V>(s, pair, f) : 0ull;
     shb[threadIdx.x] = b;
+    shf[threadIdx.x] = b > 0 ? f : 0ull;
     shc[threadIdx.x] = b > 0 ? 1u : 0u;
     __syncthreads();
     for (int h = WG / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
             shb[threadIdx.x] += shb[threadIdx.x + h];
+            shf[threadIdx.x] += shf[threadIdx.x + h];
             shc[threadIdx.x] += shc[threadIdx.x + h];
         }
         __syncthreads();
@@ -832,6 +839,7 @@ __global__ void __launch_bounds__(WG) k_pair_scalars(SolveDev s)
     if (threadIdx.x == 0 && shc[0] > 0) {
         atomicAdd(&s.stats[0], shb[0]);
         atomicAdd(&s.stats[1], (unsigned long long)shc[0]);
+        atomicAdd(&s.stats[2], shf[0]);
     }
 }
 

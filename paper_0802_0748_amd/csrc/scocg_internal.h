@@ -173,7 +173,8 @@ struct SolveDev {
     int hub_lds;               // every Hubbard operator's down-spin block fits the LDS-tiled product
     int has_red_small, has_red_big; // some rhs below / at or above 2^21 rows (per-rhs reduction width)
     int64_t hub_du_max;        // largest number of up-spin configurations among them
-    unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs
+    unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs,
+                               // [2] its algorithmic flops
 };
 
 hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_idx,

@@ -17,8 +17,8 @@ import torch
 from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scocg", "tune.json")
-BLOCKS = (8, 16, 24, 32)
-SHIFTS_PER_WG = (16, 32, 64)
+BLOCKS = (16, 24, 32, 40, 48)
+SHIFTS_PER_WG = (32, 64)
 
 
 def _key(H, n_rhs, n_shift, precision):

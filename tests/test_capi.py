@@ -38,6 +38,10 @@ def test_opts_struct_layout():
     assert ctypes.sizeof(C.Opts) == 8 + 4 * 15 + 4  # padded to 8 bytes
     assert C.Opts.window.offset == 8 + 4 * 11 and C.Opts.schedule.offset == 8 + 4 * 12
     assert ctypes.sizeof(C.PairReport) == 24
+    # the timing record: fields appended at the end keep the offsets of the earlier ones
+    assert ctypes.sizeof(C.Timing) == 64 and C.Timing.update_flops.offset == 56
+    t = C.Timing()
+    assert C.load().scocg_last_timing(ctypes.byref(t)) == 0 and t.update_flops >= 0.0
 
 
 def test_validation_rejects_bad_matrices():

@@ -53,7 +53,7 @@ def test_block_length_does_not_change_bits():
     H = S.Hamiltonian.from_csr(Hc)
     Bt = torch.from_numpy(B).cuda()
     ref = None
-    for tb in (1, 2, 4, 8, 16, 24, 32):
+    for tb in (1, 2, 4, 8, 16, 24, 32, 40, 48):
         X, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=37, seed_index=0, block=tb)
         Xn = X.cpu().numpy()
         if ref is None:
@@ -71,7 +71,7 @@ def test_block_length_does_not_change_bits_with_freezing_and_switching(precision
     H = S.Hamiltonian.from_csr(Hc)
     Bt = torch.from_numpy(B).cuda()
     ref = None
-    for tb in (1, 8, 24, 32):
+    for tb in (1, 8, 24, 32, 48):
         X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision, block=tb)
         assert rc == 0
         assert S.last_timing()["switches"] > 0
@@ -81,6 +81,34 @@ def test_block_length_does_not_change_bits_with_freezing_and_switching(precision
         else:
             assert np.array_equal(cur[1], ref[1]), tb
             assert np.array_equal(cur[0], ref[0]), tb
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_long_block_update_many_shift_groups(precision):
+    """Blocks of 24 steps and more take the LDS-staged update (64-row tiles whose eight waves
+    deal out the active pairs of up to 64 shifts), shorter blocks the register form.  With 150
+    shifts (groups of 64, 64, 22; of 37 x 4 and 2; of one), 1111 rows (a ragged last tile) and
+    pairs freezing at many different iterations, every block length and group size gives the
+    same bits."""
+    S = _S()
+    rng = np.random.default_rng(77)
+    n, M = 1111, 150
+    Hc = random_sparse_symmetric(n, 0.01, rng, diag_scale=2.0)
+    H = S.Hamiltonian.from_csr(Hc)
+    z = np.linspace(-3, 3, M) + 1j * rng.uniform(0.02, 0.5, M)
+    B = torch.from_numpy(rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))).cuda()
+    ref = None
+    for tb, g in [(16, 0), (24, 0), (32, 0), (40, 37), (48, 0), (48, 37), (48, 1)]:
+        X, rep, _, rc = S.shifted_cocg_solve(H, z, B, tol=1e-9, max_iter=4000, precision=precision, block=tb,
+                                             shifts_per_wg=g)
+        assert rc == 0, (tb, g)
+        cur = (X.cpu().numpy(), rep["iters"].copy())
+        if ref is None:
+            ref = cur
+        else:
+            assert np.array_equal(cur[1], ref[1]), (tb, g)
+            assert np.array_equal(cur[0], ref[0]), (tb, g)
+    assert len(np.unique(ref[1])) > 10
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -446,3 +474,5 @@ def test_invalid_arguments_raise():
         S.greens_diag(H, z, [50])
     with pytest.raises(ScocgError):
         S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), block=3)
+    with pytest.raises(ScocgError):
+        S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), shifts_per_wg=65)
