@@ -57,7 +57,7 @@ typedef struct {
     int32_t fixed_iter;     /* > 0: run exactly this many iterations, no freezing, no switching */
     int32_t block;          /* iterations per deferred shift update (1,2,4,8,16,24,32,40,48); 0 = automatic (48) */
     int32_t shifts_per_wg;  /* shifts one workgroup updates in the deferred update (1 .. 64); 0 = automatic
-                               (all shifts up to 64) */
+                               (up to 64 for blocks of 24 and more, up to 32 for shorter ones) */
     int32_t check_true;     /* 1: compute the FP64 true residual of every pair into the report */
     int32_t keep_tape;      /* 1: keep the solutions for backward() */
     int32_t no_graph;       /* 1: launch every kernel directly instead of replaying captured HIP graphs */

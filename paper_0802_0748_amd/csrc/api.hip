@@ -489,7 +489,9 @@ int solve(SolveRequest &rq, hipStream_t st)
     if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16 && TB != 24 && TB != 32 && TB != 40 && TB != 48)
         return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8, 16, 24, 32, 40 or 48");
     if (o.shifts_per_wg > 64) return fail(SCOCG_EINVAL, "shifts_per_wg must be at most 64");
-    int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, 64);
+    // shifts per workgroup of the update: the long-block form deals up to 64 out to its eight
+    // waves; the short-block form runs 32 per workgroup (more workgroups for few rhs)
+    int G = o.shifts_per_wg > 0 ? o.shifts_per_wg : (int)std::min<int64_t>(M, TB >= 24 ? 64 : 32);
     std::vector<int32_t> seeds(K, 0);
     for (int64_t j = 0; j < K; ++j) {
         if (rq.zper) {
