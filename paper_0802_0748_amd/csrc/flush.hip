@@ -161,9 +161,10 @@ __global__ void __launch_bounds__(WG) k_flush(const int32_t *__restrict__ blk, c
 
 // ---------------------------------------------------------------------------------------
 // Long blocks (T >= 24).  The T residuals of a 64-row tile are staged once in LDS and shared
-// by the FL_W waves of the workgroup; each wave takes every FL_W-th active slot of the shift
+// by the FL_W waves of the workgroup; each wave takes runs of NPW active slots of the shift
 // group (ranked from a ballot of the group's activity, so no loads steer the loop), keeps
-// x_k and u_k in registers and fetches the next pair's while it computes.  The coefficients
+// their x_k and u_k in registers (each history read serves all NPW) and fetches the next
+// run's while it computes.  The coefficients
 // are read with scalar loads in chunks of C steps: at each chunk boundary one wait covers
 // the chunk's coefficients and residuals, then the next chunk's loads are issued and the
 // chunk is computed while they are in flight.  (Left to itself the compiler waits for them
@@ -185,17 +186,21 @@ constexpr int FL_W = 8;  // waves per workgroup of the long-block update
         asm volatile("" ::: "memory");         \
     } while (0)
 
-// TB steps of one pair: cf is the pair's (a', b') table, lrow the thread's column of the
-// LDS history (stride 64); WX = false leaves x alone (projection mode away from the kept row)
-template <int TB, int C, typename V, bool WX>
-__device__ inline void flush_pair_steps(const V *__restrict__ cf, const V *lrow, V &x, V &u)
+// TB steps of NPW pairs: cf[q] is pair q's (a', b') table, lrow the thread's column of the
+// LDS history (stride 64), shared by the pairs; WX = false leaves x alone (projection mode
+// away from the kept row).  Each pair gets the steps in the order of k_flush.
+template <int TB, int C, int NPW, typename V, bool WX>
+__device__ inline void flush_pair_steps(const V *const (&cf)[NPW], const V *lrow, V (&x)[NPW], V (&u)[NPW])
 {
     constexpr int NC = TB / C;
-    V ca[2][C], cb[2][C], rr[2][C];
+    V ca[2][NPW][C], cb[2][NPW][C], rr[2][C];
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-        if (WX) ca[0][t] = cf[2 * t];
-        cb[0][t] = cf[2 * t + 1];
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            if (WX) ca[0][q][t] = cf[q][2 * t];
+            cb[0][q][t] = cf[q][2 * t + 1];
+        }
         rr[0][t] = lrow[t * 64];
     }
 #pragma unroll
@@ -205,23 +210,30 @@ __device__ inline void flush_pair_steps(const V *__restrict__ cf, const V *lrow,
 #pragma unroll
             for (int t = 0; t < C; ++t) {
                 const int s = (c + 1) * C + t;
-                if (WX) ca[(c + 1) & 1][t] = cf[2 * s];
-                cb[(c + 1) & 1][t] = cf[2 * s + 1];
+#pragma unroll
+                for (int q = 0; q < NPW; ++q) {
+                    if (WX) ca[(c + 1) & 1][q][t] = cf[q][2 * s];
+                    cb[(c + 1) & 1][q][t] = cf[q][2 * s + 1];
+                }
                 rr[(c + 1) & 1][t] = lrow[s * 64];
             }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int t = 0; t < C; ++t) {
-            u = cfma(cb[c & 1][t], u, rr[c & 1][t]);
-            if (WX) x = cfma(ca[c & 1][t], u, x);
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) {
+                u[q] = cfma(cb[c & 1][q][t], u[q], rr[c & 1][t]);
+                if (WX) x[q] = cfma(ca[c & 1][q][t], u[q], x[q]);
+            }
         }
         // the chunk's arithmetic stays ahead of the next boundary
-        asm volatile("" : "+v"(u.x), "+v"(u.y), "+v"(x.x), "+v"(x.y));
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) asm volatile("" : "+v"(u[q].x), "+v"(u[q].y), "+v"(x[q].x), "+v"(x[q].y));
     }
 }
 
-template <int TB, int C, typename V, bool PROJ>
+template <int TB, int C, int NPW, typename V, bool PROJ>
 __global__ void __launch_bounds__(64 * FL_W)
     k_flush_lds(const int32_t *__restrict__ blk, const double2 *__restrict__ ring, const V *__restrict__ coef,
                 const int32_t *__restrict__ nact, V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
@@ -256,11 +268,12 @@ __global__ void __launch_bounds__(64 * FL_W)
         lr[t * 64 + lane] = (t < ns && valid) ? to_v<V>(ring[(int64_t)((base + t) % R) * ntot + voff + row])
                                               : to_v<V>(cmk(0, 0));
     __syncthreads();
-    uint64_t mine = 0;  // this wave's slots: every FL_W-th active one, from rank w
+    // this wave's slots: runs of NPW consecutive active slots, every FL_W-th run, from run w
+    uint64_t mine = 0;
     {
         int rank = 0;
         for (uint64_t m = mask; m; m &= m - 1, ++rank)
-            if (rank % FL_W == w) mine |= m & (~m + 1);
+            if ((rank / NPW) % FL_W == w) mine |= m & (~m + 1);
     }
     if (mine == 0) return;
     if constexpr (!PROJ) X += M * voff;
@@ -272,50 +285,71 @@ __global__ void __launch_bounds__(64 * FL_W)
     int lo = lane;
     asm volatile("" : "+v"(lo));
     const V *lrow = lr + lo;
-    auto take = [&]() -> int64_t {
-        const int b = __builtin_ctzll(mine);
-        mine &= mine - 1;
-        return k0 + b;
-    };
-    auto fetch = [&](int64_t s, V &x, V &u) {
-        x = to_v<V>(cmk(0, 0));
-        u = x;
-        if (fresh) return;
-        u = ld_nt(P + s * n + rowc);
-        if constexpr (PROJ) {
-            if (row == prow) x = to_v<V>(Xproj[j * M + kof(s)]);
-        } else {
-            x = ld_nt(X + s * n + rowc);
+    // the next NPW slots of this wave; a missing one (-1) repeats the first, unstored
+    auto take = [&](int64_t (&sl)[NPW]) {
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            sl[q] = -1;
+            if (mine) {
+                sl[q] = k0 + __builtin_ctzll(mine);
+                mine &= mine - 1;
+            }
         }
     };
-    int64_t sn = take();
-    V xn, un;
+    auto fetch = [&](const int64_t (&sl)[NPW], V (&x)[NPW], V (&u)[NPW]) {
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            const int64_t s = sl[q] >= 0 ? sl[q] : sl[0];
+            x[q] = to_v<V>(cmk(0, 0));
+            u[q] = x[q];
+            if (fresh) continue;
+            u[q] = ld_nt(P + s * n + rowc);
+            if constexpr (PROJ) {
+                if (row == prow) x[q] = to_v<V>(Xproj[j * M + kof(s)]);
+            } else {
+                x[q] = ld_nt(X + s * n + rowc);
+            }
+        }
+    };
+    int64_t sn[NPW];
+    V xn[NPW], un[NPW];
+    take(sn);
     fetch(sn, xn, un);
     while (true) {
-        const int64_t s = sn;
-        V x = xn, u = un;
+        int64_t sl[NPW];
+        V x[NPW], u[NPW];
+        const V *cf[NPW];
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            sl[q] = sn[q];
+            x[q] = xn[q];
+            u[q] = un[q];
+            cf[q] = coef + (j * M + kof(sl[q] >= 0 ? sl[q] : sl[0])) * TB * 2;
+        }
         const bool more = mine != 0;
         if (more) {
-            sn = take();
+            take(sn);
             fetch(sn, xn, un);
         }
-        const int64_t pair = j * M + kof(s);
-        const V *cf = coef + pair * TB * 2;
-        if (with_x) flush_pair_steps<TB, C, V, true>(cf, lrow, x, u);
-        else flush_pair_steps<TB, C, V, false>(cf, lrow, x, u);
+        if (with_x) flush_pair_steps<TB, C, NPW, V, true>(cf, lrow, x, u);
+        else flush_pair_steps<TB, C, NPW, V, false>(cf, lrow, x, u);
         if (valid) {
-            st_nt(P + s * n + row, u);
-            if constexpr (PROJ) {
-                if (row == prow) Xproj[pair] = make_double2((double)x.x, (double)x.y);
-            } else {
-                st_nt(X + s * n + row, x);
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) {
+                if (sl[q] < 0) continue;
+                st_nt(P + sl[q] * n + row, u[q]);
+                if constexpr (PROJ) {
+                    if (row == prow) Xproj[j * M + kof(sl[q])] = make_double2((double)x[q].x, (double)x[q].y);
+                } else {
+                    st_nt(X + sl[q] * n + row, x[q]);
+                }
             }
         }
         if (!more) break;
     }
 }
 
-template <int TB, int C, typename V>
+template <int TB, int C, int NPW, typename V>
 static hipError_t flush_lds(const SolveDev &s, hipStream_t st)
 {
     const int G = s.shifts_per_wg;
@@ -325,21 +359,21 @@ static hipError_t flush_lds(const SolveDev &s, hipStream_t st)
     const dim3 g((unsigned)(s.nblk * (WG / 64)), (unsigned)(s.K * ng));
     const V *coef = (const V *)s.coef;
     if (s.Xproj)
-        hipLaunchKernelGGL((k_flush_lds<TB, C, V, true>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
+        hipLaunchKernelGGL((k_flush_lds<TB, C, NPW, V, true>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
                            (V *)nullptr, (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst,
                            s.R);
     else
-        hipLaunchKernelGGL((k_flush_lds<TB, C, V, false>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
+        hipLaunchKernelGGL((k_flush_lds<TB, C, NPW, V, false>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
                            (V *)s.X, (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng,
                            (const int32_t *)nullptr, s.M, s.R);
     return hipGetLastError();
 }
 
-template <int TB, int C>
+template <int TB, int C, int NPW>
 static hipError_t flush_tb_lds(const SolveDev &s, hipStream_t st)
 {
-    if (s.precision == 0) return flush_lds<TB, C, double2>(s, st);
-    return flush_lds<TB, C, float2>(s, st);
+    if (s.precision == 0) return flush_lds<TB, C, NPW, double2>(s, st);
+    return flush_lds<TB, C, NPW, float2>(s, st);
 }
 
 template <int TB, typename V, int NP>
@@ -377,11 +411,12 @@ hipError_t launch_flush(const SolveDev &s, hipStream_t st)
     case 4: return flush_tb<4>(s, st);
     case 8: return flush_tb<8>(s, st);
     case 16: return flush_tb<16>(s, st);
-    // long blocks: chunks of C steps with C * 8 scalar registers per coefficient buffer
-    case 24: return flush_tb_lds<24, 6>(s, st);
-    case 32: return flush_tb_lds<32, 4>(s, st);
-    case 40: return flush_tb_lds<40, 5>(s, st);
-    case 48: return flush_tb_lds<48, 6>(s, st);
+    // long blocks: chunks of C steps of NPW pairs, C * NPW * 8 scalar registers per
+    // coefficient buffer (two buffers); two pairs per wave share each history read
+    case 24: return flush_tb_lds<24, 3, 2>(s, st);
+    case 32: return flush_tb_lds<32, 4, 1>(s, st);
+    case 40: return flush_tb_lds<40, 5, 1>(s, st);
+    case 48: return flush_tb_lds<48, 3, 2>(s, st);
     default: return hipErrorInvalidValue;
     }
 }
