@@ -577,8 +577,9 @@ int solve(SolveRequest &rq, hipStream_t st)
     for (int64_t j = 0; j < K; ++j) {
         const DevCSR &dj = (rq.Hj.empty() ? rq.H : rq.Hj[j])->d;
         if (!dj.d_hub) continue;
-        // one partial per up-spin configuration must fit the nblk partial slots of the rhs
-        if (dj.hub_Dd > HUB_LDS_MAX || dj.n / dj.hub_Dd > s.nblk) s.hub_lds = 0;
+        // one partial per up-spin configuration must fit the rhs's own partial slots (one per
+        // 256 rows; the seed reductions read no more)
+        if (dj.hub_Dd > HUB_LDS_MAX || dj.n / dj.hub_Dd > (dj.n + 255) / 256) s.hub_lds = 0;
         s.hub_du_max = std::max<int64_t>(s.hub_du_max, dj.n / dj.hub_Dd);
     }
 

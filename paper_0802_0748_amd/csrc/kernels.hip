@@ -132,6 +132,10 @@ static constexpr int RWG_BIG = 1024;
 
 __device__ inline bool red_big(const RhsDesc &d) { return d.n >= RED_BIG_ROWS; }
 
+// Partial sums of a right-hand side's seed reductions: one per 256-row block of its own rows
+// (slots past them belong to larger right-hand sides of the batch and are not read).
+__device__ inline int64_t nparts(const RhsDesc &d) { return (d.n + WG - 1) / WG; }
+
 __device__ inline void reset_counter(uint32_t *cnt, int64_t j)
 {
     if (threadIdx.x == 0) __hip_atomic_store(&cnt[j], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -566,6 +570,7 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
     if (!any) return;
     const RhsDesc d = s.desc[j0];
     if ((d.hub != nullptr) != HUB) return;
+    if (rb * WG >= d.n) return;  // past this right-hand side's rows (its partials end before)
     const int lane = threadIdx.x & 63;
     // one 64-row slice per wave (wave-uniform, so its bookkeeping lives in scalar registers)
     const int64_t slice = rb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -643,7 +648,7 @@ __global__ void __launch_bounds__(NT) k_alpha(SolveDev s)
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
     if (red_big(s.desc[j]) != (NT == RWG_BIG)) return;
-    const double2 tot = sum_partials2<false, NT>(s.part2 + j * s.nblk, s.nblk, sh2);
+    const double2 tot = sum_partials2<false, NT>(s.part2 + j * s.nblk, nparts(s.desc[j]), sh2);
     if (threadIdx.x == 0) {
         if (cis0(tot) || cis0(st.rho)) s.seed[j].status = SEED_BREAKDOWN;
         else s.ahist[j * s.TB + st.step] = cdiv(st.rho, tot);
@@ -658,6 +663,7 @@ __global__ void __launch_bounds__(WG) k_rupd(SolveDev s)
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
     const RhsDesc d = s.desc[j];
+    if ((int64_t)blockIdx.x * WG >= d.n) return;  // past this right-hand side's rows
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     const int slot = (st.base + st.step) % s.R;
     const int nslot = (slot + 1) % s.R;
@@ -689,8 +695,9 @@ __global__ void __launch_bounds__(NT) k_beta(SolveDev s)
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
     if (red_big(s.desc[j]) != (NT == RWG_BIG)) return;
-    const double2 rho_new = sum_partials2<false, NT>(s.part2 + j * s.nblk, s.nblk, sh2);
-    const double rnorm = sqrt(sum_partials1<false, NT>(s.part1 + j * s.nblk, s.nblk, sh1));
+    const int64_t np = nparts(s.desc[j]);
+    const double2 rho_new = sum_partials2<false, NT>(s.part2 + j * s.nblk, np, sh2);
+    const double rnorm = sqrt(sum_partials1<false, NT>(s.part1 + j * s.nblk, np, sh1));
     if (threadIdx.x == 0) {
         const double2 a = s.ahist[j * s.TB + st.step];
         const double2 beta = cdiv(rho_new, st.rho);
