@@ -73,6 +73,9 @@ def parse():
                     help="write profiles/k_flush_<workload>_traffic.{json,md} from rocprofv3 counter runs")
     ap.add_argument("--trace-summary", nargs=3, metavar=("STATS_DIR", "BENCH_JSON", "COMMAND_TXT"),
                     help="write profiles/kernels_<workload>_stats.md from a rocprofv3 --stats run")
+    ap.add_argument("--clock-summary", nargs=3, metavar=("PMC_DIR", "BENCH_JSON", "COMMAND_TXT"),
+                    help="write profiles/k_flush_<workload>_clock.md from a rocprofv3 run with "
+                         "GRBM_GUI_ACTIVE and SQ_INSTS_VALU_FMA_F64")
     return ap.parse_args()
 
 
@@ -254,6 +257,49 @@ def trace_summary(args):
                       f"{line['roofline'].get('flops_per_launch', 0) / 1e9:.0f} GFLOP algorithmic per launch: "
                       f"{line['roofline']['achieved']:.1f} {line['roofline']['unit']}, "
                       f"{100 * line['roofline']['frac']:.1f} % of the {line['roofline']['bound']} peak)."]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"[bench] wrote {out}", file=sys.stderr)
+    return 0
+
+
+def clock_summary(args):
+    """Engine clock and executed FP64 multiply-add rate of the update kernel, per dispatch
+    from GRBM_GUI_ACTIVE (busy cycles, summed over the XCDs) and SQ_INSTS_VALU_FMA_F64 (wave
+    instructions, 64 lanes x 2 flops each) over each dispatch's duration."""
+    pmc_dir, bench_json, command_txt = args.clock_summary
+    line = _bench_line(bench_json)
+    with open(command_txt) as f:
+        command = f.read().strip()
+    agent = [r for r in _read_csv(_find_csv(pmc_dir, "agent_info.csv")) if r.get("Agent_Type") == "GPU"][0]
+    n_xcc, n_cu = int(agent["Num_Xcc"]), int(agent["Cu_Count"])
+    max_mhz = float(agent["Max_Engine_Clk_Fcompute"])
+    name, rows = _main_update_dispatches(_read_csv(_find_csv(pmc_dir, "counter_collection.csv")))
+    per = {}
+    for r in rows:
+        d = per.setdefault(int(r["Dispatch_Id"]), {})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    ids = sorted(per)
+    q = max(1, (len(ids) + 3) // 4)
+    parts = [("dispatches %d-%d" % (i, min(i + q, len(ids)) - 1), ids[i:i + q]) for i in range(0, len(ids), q)]
+    parts.append(("all %d" % len(ids), ids))
+    lines = [f"# Engine clock and FP64 rate of the deferred update ({args.workload} workload)", "",
+             f"Kernel `{name.split('(')[0].replace('void ', '')}`, {line['config']['workload']}, update run alone "
+             f"(serial schedule). Per dispatch: clock = GRBM_GUI_ACTIVE / {n_xcc} XCDs / duration; FP64 rate = "
+             f"SQ_INSTS_VALU_FMA_F64 x 64 lanes x 2 flops / duration; peak = {n_cu} CUs x 128 flop/clk x clock.", "",
+             "```", command, "```", "",
+             "| dispatches | mean duration (ms) | clock (GHz) | executed FP64 (TFLOP/s) | of peak at "
+             f"{max_mhz / 1e3:.1f} GHz | of peak at the measured clock |", "|---|---:|---:|---:|---:|---:|"]
+    for label, sel in parts:
+        ns = sum(per[i]["ns"] for i in sel)
+        cyc = sum(per[i]["GRBM_GUI_ACTIVE"] for i in sel) / n_xcc
+        fl = sum(per[i]["SQ_INSTS_VALU_FMA_F64"] for i in sel) * 64 * 2
+        ghz = cyc / ns
+        tfs = fl / ns / 1e3
+        lines.append(f"| {label} | {ns / len(sel) / 1e6:.2f} | {ghz:.2f} | {tfs:.1f} | "
+                     f"{100 * tfs / (n_cu * 128 * max_mhz / 1e6):.1f} % | {100 * tfs / (n_cu * 128 * ghz / 1e3):.1f} % |")
+    out = os.path.join(ROOT, "profiles", f"k_flush_{args.workload}_clock.md")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(f"[bench] wrote {out}", file=sys.stderr)
@@ -480,6 +526,8 @@ def main():
         return pmc_summary(args)
     if args.trace_summary:
         return trace_summary(args)
+    if args.clock_summary:
+        return clock_summary(args)
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
