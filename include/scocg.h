@@ -159,6 +159,31 @@ int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, 
                 const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream);
 
 /*
+ * Krylov-subspace diagonalization (Sec. 3.2, eq. Ham_in_KS) of the local Green's function,
+ * the paper's first method and the one it compares shifted COCG against: for each unit
+ * vector |j>, j = rhs_idx[c], nu steps of the three-term (Lanczos) recurrence build an
+ * orthonormal basis {K_n} of the Krylov subspace K_nu(H, |j>), in which H is the
+ * tridiagonal reduced Hamiltonian T (diagonal a_n = <K_n|H|K_n>, off-diagonal
+ * b_{n+1} = <K_{n+1}|H|K_n>); then G_jj(z_k) = [(z_k - T)^{-1}]_11, the Green's function of
+ * the subspace (exact when the subspace is invariant, an approximation otherwise, whose
+ * accuracy the paper notes is limited by the loss of orthogonality of the basis).
+ *   z       host, n_shift complex (interleaved)
+ *   rhs_idx host, n_rhs indices in [0, n)
+ *   nu      steps, 1 <= nu <= n
+ *   G       device, [n_shift][n_rhs] complex output
+ *   ab      device or NULL, [n_rhs][2][nu] doubles: a_1..a_m, then b_2..b_{m+1}
+ *           (b_{m+1} is the norm the subspace leaves out); entries past m are left as they are
+ *   dim     host or NULL, [n_rhs]: m, the subspace dimension reached: nu, or fewer when the
+ *           subspace is invariant (the recurrence stops once b_{m+1} <= 1e-12 (|a_m| + b_m))
+ * Stored matrices only: a matrix-free operator gets EINVAL.  Errors: EINVAL (null or bad
+ * arguments, index out of range, nu outside [1, n]), ENOMEM, EHIP.  Synchronous on stream
+ * when dim is requested; the timing record (scocg_last_timing) gets the wall time and
+ * iterations = steps summed over the right-hand sides.
+ */
+int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,
+                       int32_t nu, double *G, double *ab, int32_t *dim, void *stream);
+
+/*
  * G_jj(z_k) for several Hamiltonians of different sizes in one solve (a batch of
  * independent problems sharing the shift list).  Problem q has n_rhs[q] unit
  * right-hand sides; rhs_idx lists them problem after problem (indices local to the

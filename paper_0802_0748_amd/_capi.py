@@ -69,6 +69,7 @@ EXPORTED = [
     "shifted_cocg_solve",
     "greens_diag",
     "greens_diag_batched",
+    "krylov_greens_diag",
     "density_matrix_energy",
     "backward",
     "tape_free",
@@ -101,6 +102,8 @@ def load():
     lib.hubbard_upload.argtypes = [i32, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, P,
                                    ctypes.POINTER(P)]
     lib.hubbard_upload.restype = i32
+    lib.krylov_greens_diag.argtypes = [P, i64, P, i64, P, i32, P, P, P, P]
+    lib.krylov_greens_diag.restype = i32
     lib.csr_update_values.argtypes = [P, P, P]
     lib.csr_update_values.restype = i32
     lib.csr_n.argtypes = [P]

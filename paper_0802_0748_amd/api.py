@@ -209,6 +209,27 @@ def greens_diag(H: Hamiltonian, z, rhs_idx, allow_noconv=True, allow_breakdown=F
     return G, _report(rep, K, M), t, rc
 
 
+def krylov_greens_diag(H: Hamiltonian, z, rhs_idx, nu: int, device=None):
+    """Local Green's functions G_jj(z_k) by Krylov-subspace diagonalization (nu steps of the
+    three-term recurrence from each unit vector e_j, then the reduced tridiagonal Hamiltonian).
+
+    Returns (G [n_shift, n_rhs] complex128, ab [n_rhs, 2, nu] float64 with the diagonal a and
+    the off-diagonal b of each reduced Hamiltonian, dim [n_rhs] int32 subspace dimensions)."""
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    idx = np.ascontiguousarray(rhs_idx, dtype=np.int64)
+    K, M = len(idx), len(zh)
+    dev = device or torch.device("cuda")
+    G = torch.empty((M, K), dtype=torch.complex128, device=dev)
+    ab = torch.zeros((K, 2, int(nu)), dtype=torch.float64, device=dev)
+    dim = np.zeros(K, dtype=np.int32)
+    rc = lib.krylov_greens_diag(H.handle, M, zp, K, idx.ctypes.data, int(nu), G.data_ptr(), ab.data_ptr(),
+                                dim.ctypes.data, _stream_ptr())
+    C.check(rc)
+    return G, ab, dim
+
+
 def greens_diag_batched(Hs, z, rhs_lists, allow_noconv=True, allow_breakdown=False, **opts):
     """G_jj(z_k) for several Hamiltonians of different sizes in one solve.
 

@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscocg.so")
-SOURCES = ["kernels.hip", "flush.hip", "api.hip"]
-HEADERS = ["scocg_internal.h", "device_common.h"]
+SOURCES = ["kernels.hip", "flush.hip", "krylov.hip", "api.hip"]
+HEADERS = ["scocg_internal.h", "device_common.h", "krylov.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

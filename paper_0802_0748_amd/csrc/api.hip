@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/scocg.h"
+#include "krylov.h"
 #include "scocg_internal.h"
 
 using namespace scocg;
@@ -1010,6 +1011,89 @@ extern "C" int shifted_cocg_solve(scocg_csr_t H, int64_t n_shift, const double *
         }
     }
     return rc;
+}
+
+// Krylov-subspace diagonalization (Sec. 3.2): the recurrence for all right-hand sides at once
+// (groups of LZ_RB interleaved), then the subspace Green's functions.
+extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs,
+                                  const int64_t *rhs_idx, int32_t nu, double *G, double *ab, int32_t *dim,
+                                  void *stream)
+{
+    g_err.clear();
+    if (!H || !z || !rhs_idx || !G) return fail(SCOCG_EINVAL, "null argument");
+    if (H->d.d_hub) return fail(SCOCG_EINVAL, "Krylov diagonalization needs a stored matrix");
+    const int64_t n = H->d.n;
+    if (n_shift < 1 || n_rhs < 1) return fail(SCOCG_EINVAL, "n_shift and n_rhs must be positive");
+    if (nu < 1 || nu > n) return fail(SCOCG_EINVAL, "nu must be in [1, n]");
+    for (int64_t c = 0; c < n_rhs; ++c)
+        if (rhs_idx[c] < 0 || rhs_idx[c] >= n) return fail(SCOCG_EINVAL, "rhs_idx out of range");
+    for (int64_t k = 0; k < 2 * n_shift; ++k)
+        if (!std::isfinite(z[k])) return fail(SCOCG_EINVAL, "non-finite shift");
+    hipStream_t st = (hipStream_t)stream;
+    g_timing = scocg_timing{};
+    const int64_t Kp = (n_rhs + LZ_RB - 1) / LZ_RB * LZ_RB;  // padded with finished entries
+    const int64_t nblk = (n + LZ_TILE - 1) / LZ_TILE;
+    DevBuf bV0, bV1, bW0, bW1, bpart, bab, bst, bz;
+    hipError_t e = hipSuccess;
+    auto A = [&](DevBuf &b, size_t bytes) {
+        if (e == hipSuccess) e = b.alloc(bytes);
+    };
+    const size_t vbytes = (size_t)Kp * n * sizeof(double);
+    A(bV0, vbytes);
+    A(bV1, vbytes);
+    A(bW0, vbytes);
+    A(bW1, vbytes);
+    A(bpart, (size_t)Kp * nblk * sizeof(double));
+    if (!ab) A(bab, (size_t)Kp * 2 * nu * sizeof(double));
+    A(bst, (size_t)Kp * sizeof(LzRhs));
+    A(bz, (size_t)n_shift * sizeof(double2));
+    if (e != hipSuccess) return fail(SCOCG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    std::vector<LzRhs> hst(Kp);
+    for (int64_t c = 0; c < Kp; ++c) {
+        hst[c] = LzRhs{};
+        hst[c].j = c < n_rhs ? rhs_idx[c] : -1;
+        hst[c].done = c < n_rhs ? 0 : 1;
+    }
+    HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), Kp * sizeof(LzRhs), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bz.ptr, z, n_shift * sizeof(double2), hipMemcpyHostToDevice, st));
+    LzDev s{};
+    s.slice_ptr = H->d.d_slice_ptr;
+    s.slice_w = H->d.d_slice_w;
+    s.ell_col = H->d.d_ell_col;
+    s.ell_val = H->d.d_ell_val;
+    s.n = n;
+    s.K = Kp;
+    s.nblk = nblk;
+    s.nu = nu;
+    s.V[0] = bV0.as<double>();
+    s.V[1] = bV1.as<double>();
+    s.W[0] = bW0.as<double>();
+    s.W[1] = bW1.as<double>();
+    s.part = bpart.as<double>();
+    s.ab = ab ? ab : bab.as<double>();
+    s.st = bst.as<LzRhs>();
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, st));
+    for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
+    HIPCHK(launch_lanczos_greens(s, bz.as<double2>(), n_shift, n_rhs, (double2 *)G, st));
+    HIPCHK(hipEventRecord(t1, st));
+    HIPCHK(hipMemcpyAsync(hst.data(), bst.ptr, Kp * sizeof(LzRhs), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    int64_t steps = 0;
+    for (int64_t c = 0; c < n_rhs; ++c) {
+        steps += hst[c].m;
+        if (dim) dim[c] = hst[c].m;
+    }
+    g_timing.total_ms = ms;
+    g_timing.iterations = steps;
+    g_timing.blocks = nu;
+    return SCOCG_OK;
 }
 
 extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,

@@ -1,0 +1,50 @@
+// Krylov-subspace diagonalization on the device (not part of the C ABI): the three-term
+// recurrence of many unit right-hand sides' Krylov bases and the local Green's function of
+// their reduced Hamiltonians (Sec. 3.2, eq. Ham_in_KS).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace scocg {
+
+// Right-hand sides per thread of the recurrence: vectors are stored as [K / LZ_RB][n][LZ_RB]
+// (the LZ_RB right-hand sides of a group interleaved row by row), so one column and value
+// load of the stored matrix serves LZ_RB right-hand sides and their gathers are 32 B.
+constexpr int LZ_RB = 4;
+// rows per workgroup of the recurrence, one partial sum each
+constexpr int LZ_TILE = 256;
+// an invariant subspace ends the recurrence: b_{m+1} <= LZ_STOP_REL (|a_m| + b_m)
+constexpr double LZ_STOP_REL = 1e-12;
+
+struct LzRhs {
+    double bprev;  // b_n of the step in progress (0 before the first)
+    double a;      // a_n of the step in progress
+    int64_t j;     // row of the unit start vector
+    int32_t m;     // steps completed (dimension of the subspace so far)
+    int32_t done;  // recurrence finished (nu steps, or an invariant subspace)
+};
+
+struct LzDev {
+    const int64_t *slice_ptr;  // stored matrix, 64-row slices (see DevCSR)
+    const int32_t *slice_w;
+    const int32_t *ell_col;
+    const double *ell_val;
+    int64_t n;
+    int64_t K;     // right-hand sides (padded to groups of LZ_RB with finished entries)
+    int64_t nblk;  // 256-row tiles, one partial sum each
+    int32_t nu;
+    double *V[2];  // basis vectors K_n by parity of n: [K / LZ_RB][n][LZ_RB]
+    double *W[2];  // unnormalized next vectors by parity
+    double *part;  // [K][nblk] partial sums
+    double *ab;    // [K][2][nu]: a_1..a_m, then b_2..b_{m+1}
+    LzRhs *st;     // [K]
+};
+
+// one step n (0-based) of the recurrence for every unfinished right-hand side
+hipError_t launch_lanczos_step(const LzDev &s, int n, hipStream_t st);
+// G[k][r] = [(z_k - T_r)^{-1}]_11 for M shifts z (device) and K right-hand sides
+hipError_t launch_lanczos_greens(const LzDev &s, const double2 *z, int64_t M, int64_t K_out, double2 *G,
+                                 hipStream_t st);
+
+}  // namespace scocg
