@@ -169,14 +169,16 @@ int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, 
  * accuracy the paper notes is limited by the loss of orthogonality of the basis).
  *   z       host, n_shift complex (interleaved)
  *   rhs_idx host, n_rhs indices in [0, n)
- *   nu      steps, 1 <= nu <= n
+ *   nu      steps, 1 <= nu <= 2^20 (more than n is allowed: in finite precision the basis loses
+ *           orthogonality and the recurrence keeps refining, as the shifted COCG iteration
+ *           does past n steps)
  *   G       device, [n_shift][n_rhs] complex output
  *   ab      device or NULL, [n_rhs][2][nu] doubles: a_1..a_m, then b_2..b_{m+1}
  *           (b_{m+1} is the norm the subspace leaves out); entries past m are left as they are
  *   dim     host or NULL, [n_rhs]: m, the subspace dimension reached: nu, or fewer when the
  *           subspace is invariant (the recurrence stops once b_{m+1} <= 1e-12 (|a_m| + b_m))
  * Stored matrices only: a matrix-free operator gets EINVAL.  Errors: EINVAL (null or bad
- * arguments, index out of range, nu outside [1, n]), ENOMEM, EHIP.  Synchronous on stream
+ * arguments, index out of range, nu outside [1, 2^20]), ENOMEM, EHIP.  Synchronous on stream
  * when dim is requested; the timing record (scocg_last_timing) gets the wall time and
  * iterations = steps summed over the right-hand sides.
  */

@@ -150,7 +150,8 @@ def test_rejects_bad_arguments():
     Hc = random_sparse_symmetric(30, 0.2, np.random.default_rng(23))
     H = S.Hamiltonian.from_csr(Hc)
     z = np.array([0.1j])
-    for bad in [dict(rhs_idx=[30], nu=4), dict(rhs_idx=[0], nu=0), dict(rhs_idx=[0], nu=31)]:
+    for bad in [dict(rhs_idx=[30], nu=4), dict(rhs_idx=[0], nu=0), dict(rhs_idx=[0], nu=(1 << 20) + 1),
+                dict(rhs_idx=[-1], nu=4)]:
         with pytest.raises(ScocgError):
             S.krylov_greens_diag(H, z, **bad)
     with pytest.raises(ScocgError):
