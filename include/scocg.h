@@ -186,6 +186,44 @@ int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t 
                        int32_t nu, double *G, double *ab, int32_t *dim, void *stream);
 
 /*
+ * Ground state of a many-electron Hamiltonian (Sec. 2.2: the Lanczos method for an estimate,
+ * then the CG method as inverse iteration, repeated until the residual norm is small).
+ * nu steps of the three-term recurrence from x0 give the reduced Hamiltonian, whose lowest
+ * two eigenvalues E_L0 <= E_L1 are found by bisection; a second run of the same recurrence
+ * accumulates the Ritz vector of E_L0, with Rayleigh quotient theta and residual norm r.
+ * Each inverse-iteration sweep then solves (sigma - H) y = psi for the fixed shift
+ * sigma = min(E_L0 - max(0.1 (E_L1 - E_L0), 1e-6 max(1, |E_L0|)), theta - r) (below the ground
+ * state when the Ritz vector leans on it, where COCG is CG; relative residual
+ * min(1e-10, tol / 100)) and sets
+ * psi = y / ||y|| (sign kept), until ||H psi - E psi|| <= tol with E = psi . H psi, or
+ * max_sweeps sweeps.
+ *   x0      device, [n] real start vector (any norm, not orthogonal to the ground state)
+ *   psi     device, [n] complex output (imaginary parts zero), unit norm
+ *   E       host, 2 doubles: E = psi . H psi, and the estimate E_L1 of the next eigenvalue
+ *   res     host or NULL: the final ||H psi - E psi||
+ *   sweeps  host or NULL: inverse-iteration sweeps done
+ * Stored matrices only.  Errors: EINVAL (null or bad arguments, nu outside [2, 2^20]),
+ * ENOMEM, EHIP, and those of the linear solves.  Synchronous.
+ */
+int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double tol, int32_t max_sweeps, double *psi, double *E,
+                 double *res, int32_t *sweeps, void *stream);
+
+/*
+ * Fermion operator between S_z sectors of the Hubbard ring (the single-particle excitations
+ * whose spectra Sec. 4.2 computes): y = c_{site,spin} x (create = 0) or c+_{site,spin} x
+ * (create = 1) for x in the sector (L, n_up, n_dn) of hubbard_upload's basis (patterns in
+ * increasing order, index i_up * D_dn + i_dn) and y in the sector with one electron of that
+ * spin less or more.  Jordan-Wigner order: all up-spin modes (sites ascending), then all
+ * down-spin modes, so the sign is (-1)^(number of occupied modes before (site, spin)).
+ *   x  device, complex, the source sector
+ *   y  device, complex, the target sector (overwritten)
+ * Errors: EINVAL (null pointers, L outside [3, 30], counts, site or spin out of range, a
+ * target sector that does not exist), ENOMEM, EHIP.  Synchronous.
+ */
+int hubbard_fermion_op(int32_t L, int32_t n_up, int32_t n_dn, int32_t site, int32_t spin, int32_t create,
+                       const double *x, double *y, void *stream);
+
+/*
  * G_jj(z_k) for several Hamiltonians of different sizes in one solve (a batch of
  * independent problems sharing the shift list).  Problem q has n_rhs[q] unit
  * right-hand sides; rhs_idx lists them problem after problem (indices local to the

@@ -70,6 +70,8 @@ EXPORTED = [
     "greens_diag",
     "greens_diag_batched",
     "krylov_greens_diag",
+    "ground_state",
+    "hubbard_fermion_op",
     "density_matrix_energy",
     "backward",
     "tape_free",
@@ -104,6 +106,10 @@ def load():
     lib.hubbard_upload.restype = i32
     lib.krylov_greens_diag.argtypes = [P, i64, P, i64, P, i32, P, P, P, P]
     lib.krylov_greens_diag.restype = i32
+    lib.ground_state.argtypes = [P, P, i32, ctypes.c_double, i32, P, P, P, P, P]
+    lib.ground_state.restype = i32
+    lib.hubbard_fermion_op.argtypes = [i32, i32, i32, i32, i32, i32, P, P, P]
+    lib.hubbard_fermion_op.restype = i32
     lib.csr_update_values.argtypes = [P, P, P]
     lib.csr_update_values.restype = i32
     lib.csr_n.argtypes = [P]

@@ -230,6 +230,47 @@ def krylov_greens_diag(H: Hamiltonian, z, rhs_idx, nu: int, device=None):
     return G, ab, dim
 
 
+def ground_state(H: Hamiltonian, x0, nu: int = 200, tol: float = 1e-10, max_sweeps: int = 50, device=None):
+    """Lowest eigenpair of H: an estimate from nu steps of the three-term recurrence started at
+    x0, refined by inverse iteration with one-shift CG solves.  Returns (psi [n] complex128,
+    E0, E1 estimate, residual ||H psi - E0 psi||, sweeps)."""
+    _require_gpu()
+    lib = C.load()
+    dev = device or torch.device("cuda")
+    x = torch.as_tensor(x0, dtype=torch.float64).to(dev).contiguous()
+    if x.numel() != H.n:
+        raise ValueError("x0 must have one entry per row")
+    psi = torch.empty(H.n, dtype=torch.complex128, device=dev)
+    E = (ctypes.c_double * 2)()
+    res = ctypes.c_double()
+    sweeps = ctypes.c_int32()
+    rc = lib.ground_state(H.handle, x.data_ptr(), int(nu), float(tol), int(max_sweeps), psi.data_ptr(), E,
+                          ctypes.byref(res), ctypes.byref(sweeps), _stream_ptr())
+    C.check(rc)
+    return psi, E[0], E[1], res.value, sweeps.value
+
+
+def hubbard_fermion_op(L: int, n_up: int, n_dn: int, site: int, spin: int, create: bool, x: torch.Tensor):
+    """c_{site,spin} x or c+_{site,spin} x (spin 0 = up) from the sector (L, n_up, n_dn) of the
+    Hubbard ring to its neighbour sector; returns (y complex128, (n_up', n_dn'))."""
+    _require_gpu()
+    from math import comb
+
+    lib = C.load()
+    d = 1 if create else -1
+    tu, td = (n_up + d, n_dn) if spin == 0 else (n_up, n_dn + d)
+    if not (0 <= tu <= L and 0 <= td <= L):
+        raise ValueError("the target sector does not exist")
+    if x.dtype != torch.complex128 or x.numel() != comb(L, n_up) * comb(L, n_dn):
+        raise ValueError("x must be a complex128 vector of the source sector")
+    x = x.contiguous()
+    y = torch.empty(comb(L, tu) * comb(L, td), dtype=torch.complex128, device=x.device)
+    rc = lib.hubbard_fermion_op(int(L), int(n_up), int(n_dn), int(site), int(spin), int(bool(create)), x.data_ptr(),
+                                y.data_ptr(), _stream_ptr())
+    C.check(rc)
+    return y, (tu, td)
+
+
 def greens_diag_batched(Hs, z, rhs_lists, allow_noconv=True, allow_breakdown=False, **opts):
     """G_jj(z_k) for several Hamiltonians of different sizes in one solve.
 

@@ -1098,6 +1098,196 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
     return SCOCG_OK;
 }
 
+// Ground state (Sec. 2.2): the three-term recurrence from x0 estimates the lowest eigenvalues
+// (bisection on the reduced Hamiltonian) and, run a second time, accumulates the Ritz vector;
+// inverse iteration then refines it: each sweep solves (sigma - H) y = psi with one shift
+// sigma below the spectrum (where COCG is CG) and normalizes y, until ||H psi - E psi|| <= tol.
+extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double tol, int32_t max_sweeps,
+                            double *psi, double *E, double *res, int32_t *sweeps, void *stream)
+{
+    g_err.clear();
+    if (!H || !x0 || !psi || !E) return fail(SCOCG_EINVAL, "null argument");
+    if (H->d.d_hub) return fail(SCOCG_EINVAL, "the ground-state solver needs a stored matrix");
+    if (nu < 2 || nu > (1 << 20)) return fail(SCOCG_EINVAL, "nu must be in [2, 2^20]");
+    if (!(tol > 0) || max_sweeps < 0) return fail(SCOCG_EINVAL, "tol must be positive and max_sweeps >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = H->d.n;
+    const int64_t nblk = (n + LZ_TILE - 1) / LZ_TILE;
+    DevBuf bxs, bV0, bV1, bW0, bW1, bpart, bab, bst, beig, bu, bscr, bacc, by, bscal, bzb, bzx;
+    hipError_t e = hipSuccess;
+    auto A = [&](DevBuf &b, size_t bytes) {
+        if (e == hipSuccess) e = b.alloc(bytes);
+    };
+    A(bxs, n * sizeof(double));
+    for (DevBuf *b : {&bV0, &bV1, &bW0, &bW1}) A(*b, (size_t)LZ_RB * n * sizeof(double));
+    A(bpart, (size_t)LZ_RB * 2 * nblk * sizeof(double));
+    A(bab, (size_t)LZ_RB * 2 * nu * sizeof(double));
+    A(bst, LZ_RB * sizeof(LzRhs));
+    A(beig, LZ_RB * 2 * sizeof(double));
+    A(bu, (size_t)LZ_RB * nu * sizeof(double));
+    A(bscr, (size_t)LZ_RB * nu * sizeof(double));
+    A(bacc, n * sizeof(double));
+    A(by, 2 * n * sizeof(double));
+    A(bscal, 8 * sizeof(double));
+    A(bzb, n * sizeof(double2));
+    A(bzx, n * sizeof(double2));
+    if (e != hipSuccess) return fail(SCOCG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    SvDev v{};
+    v.slice_ptr = H->d.d_slice_ptr;
+    v.slice_w = H->d.d_slice_w;
+    v.ell_col = H->d.d_ell_col;
+    v.ell_val = H->d.d_ell_val;
+    v.n = n;
+    v.nblk = nblk;
+    v.part = bpart.as<double>();
+    v.scal = bscal.as<double>();
+    double *xs = bxs.as<double>();
+    HIPCHK(hipMemcpyAsync(xs, x0, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(sv_normalize(v, xs, nullptr, st));
+    // one right-hand side in a group of LZ_RB (the others finished from the start)
+    std::vector<LzRhs> hst(LZ_RB);
+    for (int c = 0; c < LZ_RB; ++c) {
+        hst[c] = LzRhs{};
+        hst[c].j = -1;
+        hst[c].done = c == 0 ? 0 : 1;
+    }
+    LzDev s{};
+    s.slice_ptr = v.slice_ptr;
+    s.slice_w = v.slice_w;
+    s.ell_col = v.ell_col;
+    s.ell_val = v.ell_val;
+    s.n = n;
+    s.K = LZ_RB;
+    s.nblk = nblk;
+    s.nu = nu;
+    s.V[0] = bV0.as<double>();
+    s.V[1] = bV1.as<double>();
+    s.W[0] = bW0.as<double>();
+    s.W[1] = bW1.as<double>();
+    s.part = bpart.as<double>();
+    s.ab = bab.as<double>();
+    s.st = bst.as<LzRhs>();
+    s.x0 = xs;
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, st));
+    HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), LZ_RB * sizeof(LzRhs), hipMemcpyHostToDevice, st));
+    for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
+    HIPCHK(launch_lanczos_lowest(s, beig.as<double>(), bu.as<double>(), bscr.as<double>(), st));
+    double eig[2];
+    HIPCHK(hipMemcpyAsync(eig, beig.ptr, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    // the same recurrence again (same bits), summing the Ritz vector sum_n u_n K_n
+    HIPCHK(hipMemsetAsync(bacc.ptr, 0, n * sizeof(double), st));
+    HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), LZ_RB * sizeof(LzRhs), hipMemcpyHostToDevice, st));
+    s.acc = bacc.as<double>();
+    s.coef = bu.as<double>();
+    for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
+    double *x = bacc.as<double>();
+    double *y = by.as<double>();
+    double *y2 = y + n;
+    HIPCHK(sv_normalize(v, x, nullptr, st));
+    HIPCHK(sv_rayleigh(v, x, y, st));
+    double sc[2];
+    HIPCHK(hipMemcpyAsync(sc, bscal.ptr, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double Ecur = sc[0], rcur = std::sqrt(std::max(sc[1], 0.0));
+    // a fixed shift below the lowest eigenvalue: a tenth of the estimated gap under the
+    // estimate, and not above theta - r, the lower end of the interval [theta - r, theta + r]
+    // that holds an eigenvalue for the Ritz pair (theta, psi) with residual norm r (the
+    // estimate is an upper bound of E0 and can be poor after few steps)
+    const double gap = eig[1] - eig[0];
+    const double sigma = std::min(eig[0] - std::max(0.1 * gap, 1e-6 * std::max(1.0, std::fabs(eig[0]))), Ecur - rcur);
+    int32_t k = 0;
+    int64_t cg_iters = 0;
+    while (rcur > tol && k < max_sweeps) {
+        HIPCHK(sv_to_complex(x, bzb.as<double2>(), n, st));
+        scocg_opts o;
+        scocg_default_opts(&o);
+        o.tol = std::min(1e-10, 1e-2 * tol);
+        o.max_iter = 1000000;
+        o.seed_index = 0;
+        o.seed_switching = 0;
+        const double zs[2] = {sigma, 0.0};
+        SolveRequest rq{};
+        rq.H = H;
+        rq.M = 1;
+        rq.K = 1;
+        rq.z = zs;
+        rq.B = bzb.as<double2>();
+        rq.o = o;
+        rq.Xout = bzx.as<double2>();
+        scocg_pair_report rp{};
+        rq.rep = &rp;
+        const int rc = solve(rq, st);
+        if (rc != SCOCG_OK) return rc;
+        cg_iters += rp.iters;
+        HIPCHK(sv_real_part(bzx.as<double2>(), y2, n, st));
+        HIPCHK(sv_normalize(v, y2, x, st));
+        std::swap(x, y2);
+        HIPCHK(sv_rayleigh(v, x, y, st));
+        HIPCHK(hipMemcpyAsync(sc, bscal.ptr, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        Ecur = sc[0];
+        rcur = std::sqrt(std::max(sc[1], 0.0));
+        ++k;
+    }
+    HIPCHK(sv_to_complex(x, (double2 *)psi, n, st));
+    HIPCHK(hipEventRecord(t1, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    E[0] = Ecur;
+    E[1] = eig[1];
+    if (res) *res = rcur;
+    if (sweeps) *sweeps = k;
+    g_timing = scocg_timing{};
+    g_timing.total_ms = ms;
+    g_timing.iterations = 2 * (int64_t)nu + cg_iters;
+    g_timing.blocks = k;
+    return SCOCG_OK;
+}
+
+// c_{site,spin} or c+_{site,spin} between sectors of the Hubbard ring (Sec. 4.2 excitations).
+extern "C" int hubbard_fermion_op(int32_t L, int32_t n_up, int32_t n_dn, int32_t site, int32_t spin, int32_t create,
+                                  const double *x, double *y, void *stream)
+{
+    g_err.clear();
+    if (!x || !y) return fail(SCOCG_EINVAL, "null argument");
+    if (L < 3 || L > 30) return fail(SCOCG_EINVAL, "L must be in [3, 30]");
+    if (n_up < 0 || n_up > L || n_dn < 0 || n_dn > L) return fail(SCOCG_EINVAL, "electron counts out of range");
+    if (site < 0 || site >= L || (spin != 0 && spin != 1)) return fail(SCOCG_EINVAL, "site or spin out of range");
+    const int d = create ? 1 : -1;
+    const int tu = spin == 0 ? n_up + d : n_up, td = spin == 1 ? n_dn + d : n_dn;
+    if (tu < 0 || tu > L || td < 0 || td > L) return fail(SCOCG_EINVAL, "the target sector does not exist");
+    const Species up = build_species(L, n_up), dn = build_species(L, n_dn);
+    const int64_t Du = (int64_t)up.conf.size(), Dd = (int64_t)dn.conf.size();
+    const int64_t Dd_t = (int64_t)build_species(L, td).conf.size();
+    const int64_t D_t = (int64_t)build_species(L, tu).conf.size() * Dd_t;
+    std::vector<int64_t> binom((L + 1) * (L + 1), 0);
+    for (int p = 0; p <= L; ++p) {
+        binom[p * (L + 1)] = 1;
+        for (int t = 1; t <= p; ++t)
+            binom[p * (L + 1) + t] = binom[(p - 1) * (L + 1) + t - 1] + (t <= p - 1 ? binom[(p - 1) * (L + 1) + t] : 0);
+    }
+    DevBuf bup, bdn, bbin;
+    hipError_t e = bup.alloc(Du * sizeof(uint32_t));
+    if (e == hipSuccess) e = bdn.alloc(Dd * sizeof(uint32_t));
+    if (e == hipSuccess) e = bbin.alloc(binom.size() * sizeof(int64_t));
+    if (e != hipSuccess) return fail(SCOCG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(bup.ptr, up.conf.data(), Du * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bdn.ptr, dn.conf.data(), Dd * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bbin.ptr, binom.data(), binom.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_fermion_op(bup.as<uint32_t>(), bdn.as<uint32_t>(), Du, Dd, bbin.as<int64_t>(), L, n_up, site, spin,
+                             create, Dd_t, D_t, (const double2 *)x, (double2 *)y, st));
+    // the tables are freed on return: wait for the kernels that read them
+    HIPCHK(hipStreamSynchronize(st));
+    return SCOCG_OK;
+}
+
 extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,
                            const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream)
 {

@@ -98,7 +98,10 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
         constexpr int LZ_CHUNK = 4;
         auto slot = [&](int32_t c, double v) {
             double x[LZ_RB];
-            if (n == 0) {
+            if (n == 0 && s.x0) {
+#pragma unroll
+                for (int b = 0; b < LZ_RB; ++b) x[b] = run[b] ? s.x0[(g * LZ_RB + b) * s.n + c] : 0.0;
+            } else if (n == 0) {
 #pragma unroll
                 for (int b = 0; b < LZ_RB; ++b) x[b] = (c == jj[b]) ? 1.0 : 0.0;
             } else {
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
         if (n == 0) {
 #pragma unroll
             for (int b = 0; b < LZ_RB; ++b) {
-                vo[b] = (row == jj[b]) ? 1.0 : 0.0;
+                vo[b] = s.x0 ? (run[b] ? s.x0[(g * LZ_RB + b) * s.n + row] : 0.0) : ((row == jj[b]) ? 1.0 : 0.0);
                 wo[b] = acc[b];
             }
         } else {
@@ -139,6 +142,14 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
         }
         Vn[row] = vo;
         Wn[row] = wo;
+        if (s.acc) {
+#pragma unroll
+            for (int b = 0; b < LZ_RB; ++b)
+                if (run[b]) {
+                    const int64_t k = g * LZ_RB + b;
+                    s.acc[k * s.n + row] = fma(s.coef[k * s.nu + n], vo[b], s.acc[k * s.n + row]);
+                }
+        }
 #pragma unroll
         for (int b = 0; b < LZ_RB; ++b) dot[b] = vo[b] * wo[b];
     }
@@ -239,6 +250,224 @@ __global__ void __launch_bounds__(WG) k_lz_greens(LzDev s, const double2 *__rest
     G[k * K + r] = g;
 }
 
+// Lowest two eigenvalues of the reduced Hamiltonian by bisection on Sturm counts (the number
+// of negative pivots of T - x), and the eigenvector of the lowest by inverse iteration with a
+// tridiagonal solve.  One thread per right-hand side.
+__device__ inline int sturm_count(const double *a, const double *b, int m, double x)
+{
+    int cnt = 0;
+    double d = 1.0;
+    for (int t = 0; t < m; ++t) {
+        const double off = t > 0 ? b[t - 1] * b[t - 1] : 0.0;
+        d = a[t] - x - (t > 0 ? off / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        cnt += d < 0.0;
+    }
+    return cnt;
+}
+
+__device__ inline double kth_eigenvalue(const double *a, const double *b, int m, int k, double lo, double hi)
+{
+    // smallest x with at least k eigenvalues below it
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(1.0, fmax(fabs(lo), fabs(hi))); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_count(a, b, m, mid) >= k) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+__global__ void __launch_bounds__(64) k_lz_lowest(LzDev s, double *eig, double *u, double *scratch)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t j = blockIdx.x;
+    const int m = s.st[j].m;
+    const double *a = s.ab + j * 2 * s.nu;
+    const double *b = a + s.nu;
+    double lo = 0, hi = 0;
+    for (int t = 0; t < m; ++t) {
+        const double r = (t > 0 ? fabs(b[t - 1]) : 0.0) + (t + 1 < m ? fabs(b[t]) : 0.0);
+        lo = t == 0 ? a[t] - r : fmin(lo, a[t] - r);
+        hi = t == 0 ? a[t] + r : fmax(hi, a[t] + r);
+    }
+    lo -= 1e-12 * fmax(1.0, fabs(lo));
+    hi += 1e-12 * fmax(1.0, fabs(hi));
+    const double e0 = kth_eigenvalue(a, b, m, 1, lo, hi);
+    const double e1 = m > 1 ? kth_eigenvalue(a, b, m, 2, lo, hi) : e0;
+    eig[2 * j] = e0;
+    eig[2 * j + 1] = e1;
+    // (T - e0) v = w by the tridiagonal elimination, twice from w = 1
+    double *v = u + j * s.nu;
+    double *cp = scratch + j * s.nu;
+    // a pivot that vanishes (the shift is an eigenvalue) is replaced by 1e-14 of the scale:
+    // the solve then amplifies the eigenvector by about 1e14, which the normalization removes
+    const double tiny = 1e-14 * fmax(1.0, fabs(e0));
+    auto guard = [&](double d) { return fabs(d) < tiny ? (d < 0 ? -tiny : tiny) : d; };
+    for (int t = 0; t < s.nu; ++t) v[t] = t < m ? 1.0 : 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        double den = guard(a[0] - e0);
+        cp[0] = m > 1 ? b[0] / den : 0.0;
+        v[0] = v[0] / den;
+        for (int t = 1; t < m; ++t) {
+            den = guard(a[t] - e0 - b[t - 1] * cp[t - 1]);
+            cp[t] = t + 1 < m ? b[t] / den : 0.0;
+            v[t] = (v[t] - b[t - 1] * v[t - 1]) / den;
+        }
+        for (int t = m - 2; t >= 0; --t) v[t] -= cp[t] * v[t + 1];
+        double vmax = 0;
+        for (int t = 0; t < m; ++t) vmax = fmax(vmax, fabs(v[t]));
+        double nn = 0;
+        for (int t = 0; t < m; ++t) {
+            v[t] /= vmax;
+            nn += v[t] * v[t];
+        }
+        const double inv = 1.0 / sqrt(nn);
+        for (int t = 0; t < m; ++t) v[t] *= inv;
+    }
+}
+
+// ---- single vector on the stored matrix ----
+__global__ void __launch_bounds__(WG) k_sv_matvec(SvDev s, const double *__restrict__ x, double *__restrict__ y)
+{
+    __shared__ double sh[WG];
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double d = 0;
+    if (row < s.n) {
+        const int64_t slice = row >> 6;
+        const int lane = (int)(row & 63);
+        const int64_t off = s.slice_ptr[slice];
+        const int w = s.slice_w[slice];
+        double acc = 0;
+        for (int k = 0; k < w; ++k) {
+            const int64_t e = off + (int64_t)k * 64 + lane;
+            acc = fma(s.ell_val[e], x[s.ell_col[e]], acc);
+        }
+        y[row] = acc;
+        d = x[row] * acc;
+    }
+    sh[threadIdx.x] = d;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s.part[blockIdx.x] = sh[0];
+}
+
+// partials of ||y - E x||^2 (E = scal[0]) into part, or of ||x||^2 and x . ref into part, part + nblk
+__global__ void __launch_bounds__(WG) k_sv_resid(SvDev s, const double *__restrict__ x, const double *__restrict__ y)
+{
+    __shared__ double sh[WG];
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double d = 0;
+    if (row < s.n) {
+        const double r = fma(-s.scal[0], x[row], y[row]);
+        d = r * r;
+    }
+    sh[threadIdx.x] = d;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s.part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(WG) k_sv_norm_dot(SvDev s, const double *__restrict__ x, const double *__restrict__ ref)
+{
+    __shared__ double sh[2][WG];
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double nn = 0, dd = 0;
+    if (row < s.n) {
+        nn = x[row] * x[row];
+        dd = ref ? x[row] * ref[row] : 0.0;
+    }
+    sh[0][threadIdx.x] = nn;
+    sh[1][threadIdx.x] = dd;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        s.part[blockIdx.x] = sh[0][0];
+        s.part[s.nblk + blockIdx.x] = sh[1][0];
+    }
+}
+
+// scal[slot] = sum of the nblk partials at part + off (fixed order)
+__global__ void __launch_bounds__(WG) k_sv_sum(SvDev s, int64_t off, int slot)
+{
+    __shared__ double sh[WG];
+    const double v = sum_tiles(s.part + off, s.nblk, sh);
+    if (threadIdx.x == 0) s.scal[slot] = v;
+}
+
+__global__ void __launch_bounds__(WG) k_sv_scale(SvDev s, double *__restrict__ x)
+{
+    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (row >= s.n) return;
+    const double f = (s.scal[3] < 0 ? -1.0 : 1.0) / sqrt(s.scal[2]);
+    x[row] *= f;
+}
+
+__global__ void k_to_complex(const double *__restrict__ x, double2 *__restrict__ z, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = cmk(x[i], 0.0);
+}
+
+__global__ void k_real_part(const double2 *__restrict__ z, double *__restrict__ x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = z[i].x;
+}
+
+// ---- fermion operator between Hubbard sectors ----
+// Rank of an L-bit pattern among the patterns with the same number of set bits, in
+// increasing integer order: sum over its set bits p_0 < p_1 < ... of C(p_t, t + 1).
+__device__ inline int64_t pattern_rank(uint32_t s, const int64_t *binom, int L)
+{
+    int64_t r = 0;
+    int t = 0;
+    for (int p = 0; p < L; ++p)
+        if ((s >> p) & 1u) {
+            ++t;
+            r += binom[p * (L + 1) + t];
+        }
+    return r;
+}
+
+__global__ void k_zero2(double2 *y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = cmk(0, 0);
+}
+
+__global__ void k_fermion_op(const uint32_t *__restrict__ up, const uint32_t *__restrict__ dn, int64_t Du, int64_t Dd,
+                             const int64_t *__restrict__ binom, int L, int n_up, int site, int spin, int create,
+                             int64_t Dd_tgt, const double2 *__restrict__ x, double2 *__restrict__ y)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Du * Dd) return;
+    const int64_t iu = r / Dd, idn = r % Dd;
+    const uint32_t su = up[iu], sd = dn[idn];
+    const uint32_t bit = 1u << site;
+    const uint32_t s = spin == 0 ? su : sd;
+    const bool occupied = (s & bit) != 0;
+    if (occupied == (create != 0)) return;
+    // Jordan-Wigner order: all up-spin modes (sites ascending), then all down-spin modes
+    const int before = __popc(s & (bit - 1u)) + (spin == 0 ? 0 : n_up);
+    const double sg = (before & 1) ? -1.0 : 1.0;
+    int64_t k;
+    if (spin == 0) k = pattern_rank(su ^ bit, binom, L) * Dd_tgt + idn;
+    else k = iu * Dd_tgt + pattern_rank(sd ^ bit, binom, L);
+    y[k] = make_double2(sg * x[r].x, sg * x[r].y);
+}
+
 hipError_t launch_lanczos_step(const LzDev &s, int n, hipStream_t st)
 {
     const int64_t groups = s.K / LZ_RB;
@@ -258,6 +487,56 @@ hipError_t launch_lanczos_greens(const LzDev &s, const double2 *z, int64_t M, in
     if (total == 0) return hipSuccess;
     if ((total + WG - 1) / WG > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_lz_greens, dim3((unsigned)((total + WG - 1) / WG)), dim3(WG), 0, st, s, z, M, K_out, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos_lowest(const LzDev &s, double *eig, double *u, double *scratch, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_lowest, dim3((unsigned)s.K), dim3(64), 0, st, s, eig, u, scratch);
+    return hipGetLastError();
+}
+
+hipError_t sv_rayleigh(const SvDev &s, const double *x, double *y, hipStream_t st)
+{
+    const dim3 g((unsigned)s.nblk);
+    hipLaunchKernelGGL(k_sv_matvec, g, dim3(WG), 0, st, s, x, y);
+    hipLaunchKernelGGL(k_sv_sum, dim3(1), dim3(WG), 0, st, s, (int64_t)0, 0);
+    hipLaunchKernelGGL(k_sv_resid, g, dim3(WG), 0, st, s, x, (const double *)y);
+    hipLaunchKernelGGL(k_sv_sum, dim3(1), dim3(WG), 0, st, s, (int64_t)0, 1);
+    return hipGetLastError();
+}
+
+hipError_t sv_normalize(const SvDev &s, double *x, const double *ref, hipStream_t st)
+{
+    const dim3 g((unsigned)s.nblk);
+    hipLaunchKernelGGL(k_sv_norm_dot, g, dim3(WG), 0, st, s, (const double *)x, ref);
+    hipLaunchKernelGGL(k_sv_sum, dim3(1), dim3(WG), 0, st, s, (int64_t)0, 2);
+    hipLaunchKernelGGL(k_sv_sum, dim3(1), dim3(WG), 0, st, s, s.nblk, 3);
+    hipLaunchKernelGGL(k_sv_scale, g, dim3(WG), 0, st, s, x);
+    return hipGetLastError();
+}
+
+hipError_t sv_to_complex(const double *x, double2 *z, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_complex, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st, x, z, n);
+    return hipGetLastError();
+}
+
+hipError_t sv_real_part(const double2 *z, double *x, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_real_part, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st, z, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fermion_op(const uint32_t *up_src, const uint32_t *dn_src, int64_t Du, int64_t Dd,
+                             const int64_t *binom, int L, int n_up, int site, int spin, int create,
+                             int64_t Dd_tgt, int64_t D_tgt, const double2 *x, double2 *y, hipStream_t st)
+{
+    const int64_t D = Du * Dd;
+    if ((D + WG - 1) / WG > 0x7fffffffLL || (D_tgt + WG - 1) / WG > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_zero2, dim3((unsigned)((D_tgt + WG - 1) / WG)), dim3(WG), 0, st, y, D_tgt);
+    hipLaunchKernelGGL(k_fermion_op, dim3((unsigned)((D + WG - 1) / WG)), dim3(WG), 0, st, up_src, dn_src, Du, Dd, binom, L,
+                       n_up, site, spin, create, Dd_tgt, x, y);
     return hipGetLastError();
 }
 
