@@ -111,8 +111,8 @@ def test_long_block_update_many_shift_groups(precision):
     assert len(np.unique(ref[1])) > 10
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_overlapped_update_equals_serial_bitwise(precision):
+@pytest.mark.parametrize("precision,block", [("fp64", 8), ("fp32", 8), ("fp64", 48)])
+def test_overlapped_update_equals_serial_bitwise(precision, block):
     """The deferred update of a block overlaps the next block's iterations on a second stream,
     and a seed switch waits out one block: per right-hand side the arithmetic is unchanged, so
     the results equal the serial schedule's bit for bit (with freezing and switching)."""
@@ -124,7 +124,7 @@ def test_overlapped_update_equals_serial_bitwise(precision):
     for schedule in ("overlap", "serial"):
         # seed 5 has the largest Im z: it converges first, so the seed switches
         X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision,
-                                             schedule=schedule, block=8, seed_index=5)
+                                             schedule=schedule, block=block, seed_index=5)
         assert rc == 0
         runs.append((X.cpu().numpy(), rep["iters"].copy(), S.last_timing()["switches"]))
     assert runs[0][2] == runs[1][2] and runs[0][2] > 0
