@@ -162,9 +162,15 @@ def test_graph_replay_equals_direct_launches_bitwise(precision):
     assert np.array_equal(repg["iters"], repd["iters"])
 
 
-def test_batched_equals_single_rhs_bitwise():
+@pytest.mark.parametrize("n_rhs", [3, 8])
+def test_batched_equals_single_rhs_bitwise(n_rhs):
+    """Right-hand sides run two to a seed-kernel thread (interleaved directions; with three,
+    the last one alone): each gets the bits of its own solve."""
     S = _S()
     Hc, z, B = _problem(500, 3)
+    if n_rhs > B.shape[0]:
+        rng = np.random.default_rng(33)
+        B = np.concatenate([B, rng.normal(size=(n_rhs - B.shape[0], Hc.n)) + 1j * rng.normal(size=(n_rhs - 3, Hc.n))])
     H = S.Hamiltonian.from_csr(Hc)
     Xb, repb, _, _ = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=1e-10, max_iter=3000)
     Xb = Xb.cpu().numpy()
