@@ -234,8 +234,9 @@ def trace_summary(args):
     with open(command_txt) as f:
         command = f.read().strip()
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    out = os.path.join(ROOT, "profiles", f"kernels_{args.workload}_stats.md")
-    lines = [f"# Kernel time, {args.workload} benchmark workload", "",
+    wl = args.workload + ("_matrix_free" if args.matrix_free else "")
+    out = os.path.join(ROOT, "profiles", f"kernels_{wl}_stats.md")
+    lines = [f"# Kernel time, {wl.replace('_', ' ')} benchmark workload", "",
              f"{line['config']['workload']}; bench.py reported {line['value']:.1f} {line['unit']} "
              f"({line['ms_per_step'] / 1e3:.2f} s per solve) in this profiled run.", "",
              "```", command, "```", "",
@@ -249,7 +250,7 @@ def trace_summary(args):
         trace = _read_csv(_find_csv(stats_dir, "kernel_trace.csv"))
     except FileNotFoundError:
         trace = []
-    if trace:
+    if trace and "avg_launch_ms" in line.get("roofline", {}):
         # the benchmark solve's update launches: the busiest k_flush instance at its largest grid
         name, disp = _main_update_dispatches(trace)
         avg_ms = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in disp) / len(disp) / 1e6
