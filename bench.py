@@ -54,6 +54,8 @@ def parse():
                     help="deferred update in order with the seed iterations, or overlapped with the next block")
     ap.add_argument("--matrix-free", action="store_true",
                     help="hubbard workload: apply H from per-species hopping tables (hubbard_upload)")
+    ap.add_argument("--stored-ground-state", action="store_true",
+                    help="manybody workload: ground state on the stored sector matrix instead of the operator")
     ap.add_argument("--window", type=int, default=0,
                     help="G_jj workloads (cubic, batch): shifts per rhs whose full directions are kept "
                          "(seed candidates); the others cost scalar work only.  0: all")
@@ -496,7 +498,7 @@ def krylov_cpu_baseline(p, nu, K, M):
 
 def bench_manybody(args, S, torch):
     """Ground state and ionization spectrum of the 14-site extended Hubbard ring (Sec. 2.2 and
-    Sec. 4.2): the 7+7 sector (11,778,624 states, stored matrix) gets its ground state from
+    Sec. 4.2): the 7+7 sector (11,778,624 states, matrix-free operator) gets its ground state from
     200 steps of the three-term recurrence and CG inverse iteration to ||H psi - E0 psi|| <=
     1e-10; b = c_{0,up}|psi0> then lies in the 6+7 sector (10,306,296 states, matrix-free
     operator), where shifted COCG gives <b|((E0 - w) + i eta - H)^{-1}|b> at 128 energies
@@ -506,11 +508,15 @@ def bench_manybody(args, S, torch):
 
     L, nu, nd = 14, 7, 7
     t0 = time.perf_counter()
-    Hc = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0)
-    H = S.Hamiltonian.from_csr(Hc)
-    print(f"[bench] workload manybody: sector 7+7 of 14 sites, n={Hc.n} nnz={Hc.nnz}, built in "
+    # the operator or the stored sector matrix (--stored-ground-state) give the same bits
+    if args.stored_ground_state:
+        H = S.Hamiltonian.from_csr(hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0))
+    else:
+        H = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    form = "stored matrix" if args.stored_ground_state else "matrix-free operator"
+    print(f"[bench] workload manybody: sector 7+7 of 14 sites, n={H.n} nnz={H.nnz} ({form}), built in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    x0 = np.random.default_rng(0).normal(size=Hc.n)
+    x0 = np.random.default_rng(0).normal(size=H.n)
     S.ground_state(S.Hamiltonian.from_csr(hubbard_ring(6, 3, 3)), np.ones(400), nu=20, tol=1e-8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -546,8 +552,9 @@ def bench_manybody(args, S, torch):
         "ms_per_step": 1e3 * (t_gs + t_sp), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "extended Hubbard ring L=14, t=1, U=4, V=1: ground state of 7+7 "
-                               f"(n={Hc.n}), ionization spectrum of c_(0,up) in 6+7 (n={Hm.n}, matrix-free), "
-                               f"{M} energies, eta=0.05", "n": int(Hc.n), "n_target": int(Hm.n), "n_shift": M},
+                               f"(n={H.n}, {form}), ionization spectrum of c_(0,up) in 6+7 (n={Hm.n}, "
+                               f"matrix-free), {M} energies, eta=0.05", "n": int(H.n), "n_target": int(Hm.n),
+                   "n_shift": M},
         "ground_state": {"E0": E0, "E1_estimate": E1, "residual": res, "sweeps": sweeps, "cg_iterations": int(cg),
                          "seconds": t_gs},
         "spectrum": {"seconds": t_sp, "converged": conv, "total_weight": occ, "occupation": nu / L,

@@ -177,8 +177,9 @@ int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, 
  *           (b_{m+1} is the norm the subspace leaves out); entries past m are left as they are
  *   dim     host or NULL, [n_rhs]: m, the subspace dimension reached: nu, or fewer when the
  *           subspace is invariant (the recurrence stops once b_{m+1} <= 1e-12 (|a_m| + b_m))
- * Stored matrices only: a matrix-free operator gets EINVAL.  Errors: EINVAL (null or bad
- * arguments, index out of range, nu outside [1, 2^20]), ENOMEM, EHIP.  Synchronous on stream
+ * H is a stored matrix or a matrix-free Hubbard operator (whose rows give the same sums,
+ * so the same coefficients bit for bit).  Errors: EINVAL (null or bad arguments, index out of
+ * range, nu outside [1, 2^20]), ENOMEM, EHIP.  Synchronous on stream
  * when dim is requested; the timing record (scocg_last_timing) gets the wall time and
  * iterations = steps summed over the right-hand sides.
  */
@@ -202,8 +203,9 @@ int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t 
  *   E       host, 2 doubles: E = psi . H psi, and the estimate E_L1 of the next eigenvalue
  *   res     host or NULL: the final ||H psi - E psi||
  *   sweeps  host or NULL: inverse-iteration sweeps done
- * Stored matrices only.  Errors: EINVAL (null or bad arguments, nu outside [2, 2^20]),
- * ENOMEM, EHIP, and those of the linear solves.  Synchronous.
+ * H is a stored matrix or a matrix-free Hubbard operator (the same results bit for bit).
+ * Errors: EINVAL (null or bad arguments, nu outside [2, 2^20]), ENOMEM, EHIP, and those of the
+ * linear solves.  Synchronous.
  */
 int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double tol, int32_t max_sweeps, double *psi, double *E,
                  double *res, int32_t *sweeps, void *stream);

@@ -1021,7 +1021,6 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
 {
     g_err.clear();
     if (!H || !z || !rhs_idx || !G) return fail(SCOCG_EINVAL, "null argument");
-    if (H->d.d_hub) return fail(SCOCG_EINVAL, "Krylov diagonalization needs a stored matrix");
     const int64_t n = H->d.n;
     if (n_shift < 1 || n_rhs < 1) return fail(SCOCG_EINVAL, "n_shift and n_rhs must be positive");
     // finite-precision recurrences run past n (the basis loses orthogonality); the limit keeps
@@ -1059,6 +1058,7 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
     HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), Kp * sizeof(LzRhs), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bz.ptr, z, n_shift * sizeof(double2), hipMemcpyHostToDevice, st));
     LzDev s{};
+    s.hub = H->d.d_hub;
     s.slice_ptr = H->d.d_slice_ptr;
     s.slice_w = H->d.d_slice_w;
     s.ell_col = H->d.d_ell_col;
@@ -1107,7 +1107,6 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
 {
     g_err.clear();
     if (!H || !x0 || !psi || !E) return fail(SCOCG_EINVAL, "null argument");
-    if (H->d.d_hub) return fail(SCOCG_EINVAL, "the ground-state solver needs a stored matrix");
     if (nu < 2 || nu > (1 << 20)) return fail(SCOCG_EINVAL, "nu must be in [2, 2^20]");
     if (!(tol > 0) || max_sweeps < 0) return fail(SCOCG_EINVAL, "tol must be positive and max_sweeps >= 0");
     hipStream_t st = (hipStream_t)stream;
@@ -1133,6 +1132,7 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     A(bzx, n * sizeof(double2));
     if (e != hipSuccess) return fail(SCOCG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
     SvDev v{};
+    v.hub = H->d.d_hub;
     v.slice_ptr = H->d.d_slice_ptr;
     v.slice_w = H->d.d_slice_w;
     v.ell_col = H->d.d_ell_col;
@@ -1152,6 +1152,7 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
         hst[c].done = c == 0 ? 0 : 1;
     }
     LzDev s{};
+    s.hub = v.hub;
     s.slice_ptr = v.slice_ptr;
     s.slice_w = v.slice_w;
     s.ell_col = v.ell_col;

@@ -308,8 +308,6 @@ __device__ inline const __attribute__((address_space(1))) T *gptr(const T *p)
     return (const __attribute__((address_space(1))) T *)p;
 }
 
-// Occupations of the right neighbours: bit i of the result is bit (i + 1) mod L of c.
-__device__ inline uint32_t ring_next(uint32_t c, int L) { return ((c >> 1) | ((c & 1u) << (L - 1))) & ((1u << L) - 1u); }
 
 // Row `row` of H p for the matrix-free Hubbard operator, for RB right-hand sides whose p at
 // row c is pv[RB * c + b].  The terms are added in the column order of the stored matrix

@@ -8,6 +8,8 @@
 
 namespace scocg {
 
+struct HubbardOp;
+
 // Right-hand sides per thread of the recurrence: vectors are stored as [K / LZ_RB][n][LZ_RB]
 // (the LZ_RB right-hand sides of a group interleaved row by row), so one column and value
 // load of the stored matrix serves LZ_RB right-hand sides and their gathers are 32 B.
@@ -26,6 +28,7 @@ struct LzRhs {
 };
 
 struct LzDev {
+    const HubbardOp *hub;      // matrix-free operator (device), or null for the stored matrix
     const int64_t *slice_ptr;  // stored matrix, 64-row slices (see DevCSR)
     const int32_t *slice_w;
     const int32_t *ell_col;
@@ -44,9 +47,10 @@ struct LzDev {
     const double *coef;  // [K][nu] with acc
 };
 
-// Single real vector of n rows on the stored matrix; one partial per 256-row tile, summed
-// in fixed order by one workgroup into the device scalars scal[].
+// Single real vector of n rows on the stored matrix or the matrix-free operator; one partial
+// per 256-row tile, summed in fixed order by one workgroup into the device scalars scal[].
 struct SvDev {
+    const HubbardOp *hub;  // matrix-free operator (device), or null
     const int64_t *slice_ptr;
     const int32_t *slice_w;
     const int32_t *ell_col;

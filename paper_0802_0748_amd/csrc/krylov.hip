@@ -87,16 +87,8 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
     double dot[LZ_RB] = {0, 0, 0, 0};
     if (row < s.n) {
         double acc[LZ_RB] = {0, 0, 0, 0};
-        const int64_t slice = row >> 6;
-        const int lane = (int)(row & 63);
-        const int64_t off = s.slice_ptr[slice];
-        const int w = s.slice_w[slice];
-        const int32_t *colp = s.ell_col + off + lane;
-        const double *valp = s.ell_val + off + lane;
-        // slots in the stored order; column and value loads of LZ_CHUNK slots are issued
-        // before their gathers
-        constexpr int LZ_CHUNK = 4;
-        auto slot = [&](int32_t c, double v) {
+        // one term of the row: acc += v x[c]
+        auto slot = [&](int64_t c, double v) {
             double x[LZ_RB];
             if (n == 0 && s.x0) {
 #pragma unroll
@@ -112,19 +104,33 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
 #pragma unroll
             for (int b = 0; b < LZ_RB; ++b) acc[b] = fma(v, x[b], acc[b]);
         };
-        int k = 0;
-        for (; k + LZ_CHUNK <= w; k += LZ_CHUNK) {
-            int32_t c[LZ_CHUNK];
-            double v[LZ_CHUNK];
+        if (s.hub) {
+            // the operator's terms in the stored row's column order: the same sums
+            hubbard_row_terms(s.hub, row, slot);
+        } else {
+            const int64_t slice = row >> 6;
+            const int lane = (int)(row & 63);
+            const int64_t off = s.slice_ptr[slice];
+            const int w = s.slice_w[slice];
+            const int32_t *colp = s.ell_col + off + lane;
+            const double *valp = s.ell_val + off + lane;
+            // slots in the stored order; column and value loads of LZ_CHUNK slots are issued
+            // before their gathers
+            constexpr int LZ_CHUNK = 4;
+            int k = 0;
+            for (; k + LZ_CHUNK <= w; k += LZ_CHUNK) {
+                int32_t c[LZ_CHUNK];
+                double v[LZ_CHUNK];
 #pragma unroll
-            for (int u = 0; u < LZ_CHUNK; ++u) {
-                c[u] = colp[(int64_t)(k + u) * 64];
-                v[u] = valp[(int64_t)(k + u) * 64];
+                for (int u = 0; u < LZ_CHUNK; ++u) {
+                    c[u] = colp[(int64_t)(k + u) * 64];
+                    v[u] = valp[(int64_t)(k + u) * 64];
+                }
+#pragma unroll
+                for (int u = 0; u < LZ_CHUNK; ++u) slot(c[u], v[u]);
             }
-#pragma unroll
-            for (int u = 0; u < LZ_CHUNK; ++u) slot(c[u], v[u]);
+            for (; k < w; ++k) slot(colp[(int64_t)k * 64], valp[(int64_t)k * 64]);
         }
-        for (; k < w; ++k) slot(colp[(int64_t)k * 64], valp[(int64_t)k * 64]);
         d4v vo, wo;
         if (n == 0) {
 #pragma unroll
@@ -333,14 +339,18 @@ __global__ void __launch_bounds__(WG) k_sv_matvec(SvDev s, const double *__restr
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     double d = 0;
     if (row < s.n) {
-        const int64_t slice = row >> 6;
-        const int lane = (int)(row & 63);
-        const int64_t off = s.slice_ptr[slice];
-        const int w = s.slice_w[slice];
         double acc = 0;
-        for (int k = 0; k < w; ++k) {
-            const int64_t e = off + (int64_t)k * 64 + lane;
-            acc = fma(s.ell_val[e], x[s.ell_col[e]], acc);
+        if (s.hub) {
+            hubbard_row_terms(s.hub, row, [&](int64_t c, double v) { acc = fma(v, x[c], acc); });
+        } else {
+            const int64_t slice = row >> 6;
+            const int lane = (int)(row & 63);
+            const int64_t off = s.slice_ptr[slice];
+            const int w = s.slice_w[slice];
+            for (int k = 0; k < w; ++k) {
+                const int64_t e = off + (int64_t)k * 64 + lane;
+                acc = fma(s.ell_val[e], x[s.ell_col[e]], acc);
+            }
         }
         y[row] = acc;
         d = x[row] * acc;

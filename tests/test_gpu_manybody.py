@@ -82,6 +82,24 @@ def test_ground_state_matches_dense_diagonalization(L, nu, nd, U, V, steps):
         assert sweeps >= 1
 
 
+@pytest.mark.parametrize("steps", [120, 16])
+def test_ground_state_matrix_free_equals_stored(steps):
+    """The ground state on the matrix-free operator: its rows give the stored matrix's sums
+    and the inverse-iteration solves its products, so psi and E are the same bits."""
+    S = _S()
+    L, nu, nd = 10, 5, 4
+    Hc = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    Hm = S.Hamiltonian.from_csr(Hc)
+    Ho = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    x0 = np.random.default_rng(5).normal(size=Hc.n)
+    pm, Em, E1m, rm, sm = S.ground_state(Hm, x0, nu=steps, tol=1e-10)
+    po, Eo, E1o, ro, so = S.ground_state(Ho, x0, nu=steps, tol=1e-10)
+    print(f"{steps} steps: E0 {Eo:.12f}, residual {ro:.1e}, sweeps {so}")
+    assert (Eo, E1o, ro, so) == (Em, E1m, rm, sm)
+    assert np.array_equal(po.cpu().numpy(), pm.cpu().numpy())
+    assert ro <= 1e-10
+
+
 def test_ionization_spectrum_from_the_ground_state():
     """b = c_{0,up}|psi0> in the sector with one up electron less; the ionization Green's
     function <b|((E0 - w) + i eta - H)^{-1}|b> over a range of energies, by the shifted COCG
