@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscocg.so")
 SOURCES = ["kernels.hip", "flush.hip", "krylov.hip", "api.hip"]
-HEADERS = ["scocg_internal.h", "device_common.h", "krylov.h"]
+HEADERS = ["scocg_internal.h", "device_common.h", "krylov.h", "hubbard_rows.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

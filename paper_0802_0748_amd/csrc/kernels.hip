@@ -12,6 +12,7 @@
 // the partials in index order, so results do not depend on scheduling and a rhs gives the
 // same bits whether it is solved alone or in a batch.
 #include "device_common.h"
+#include "hubbard_rows.h"
 
 namespace scocg {
 

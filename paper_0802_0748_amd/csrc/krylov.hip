@@ -8,6 +8,7 @@
 // Start vectors are unit vectors, so every basis vector is real.  Sums are fixed-order
 // (per 256-row tile, then the tiles in index order), so results do not depend on scheduling.
 #include "device_common.h"
+#include "hubbard_rows.h"
 #include "krylov.h"
 
 namespace scocg {
