@@ -124,3 +124,38 @@ def test_ionization_spectrum_from_the_ground_state():
     assert np.max(np.abs(G - ref) / np.abs(ref)) < 1e-8
     # the spectral weight sums to the occupation <psi0|n_{0,up}|psi0> = N_up / L on the ring
     assert abs(float((b.conj() @ b).real) - nu / L) < 1e-10
+
+
+def test_affinity_spectrum_and_the_total_sum_rule():
+    """b' = c+_{0,up}|psi0> in the sector with one up electron more: the addition Green's
+    function <b'|((E0 + w) + i eta - H)^{-1}|b'> against dense solves of the reference; the
+    removal and addition weights <b|b> + <b'|b'> add up to 1 (the anticommutator
+    {c, c+} = 1 in the ground state), and both spectral functions are non-negative."""
+    S = _S()
+    L, nu, nd = 8, 4, 4
+    Hc = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    H = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    psi, E0, _, res, _ = S.ground_state(H, np.random.default_rng(2).normal(size=Hc.n), nu=120, tol=1e-11)
+    b, sec_m = S.hubbard_fermion_op(L, nu, nd, 0, 0, False, psi)
+    bp, sec_p = S.hubbard_fermion_op(L, nu, nd, 0, 0, True, psi)
+    assert sec_p == (nu + 1, nd)
+    w = np.linspace(-8, 8, 33)
+    eta = 0.1
+    Hp = S.Hamiltonian.hubbard(L, *sec_p, t=1.0, U=4.0, V=1.0)
+    Xp, _, _, rc = S.shifted_cocg_solve(Hp, (E0 + w) + 1j * eta, bp[None, :], tol=1e-12, max_iter=20000)
+    assert rc == 0
+    Gp = (Xp[0] @ bp).cpu().numpy()
+    E_ref, psi_ref, _ = MB.ground_state(Hc.to_dense())
+    sgn = np.sign(psi.cpu().numpy().real @ psi_ref)
+    bp_ref, _ = MB.fermion_op(L, nu, nd, 0, 0, True, sgn * psi_ref.astype(complex))
+    Hp_dense = hubbard_ring(L, *sec_p, t=1.0, U=4.0, V=1.0).to_dense()
+    ref = MB.projected_resolvent(Hp_dense, bp_ref.real, (E_ref + w) + 1j * eta)
+    assert np.max(np.abs(Gp - ref) / np.abs(ref)) < 1e-8
+    Xm, _, _, rc = S.shifted_cocg_solve(S.Hamiltonian.hubbard(L, *sec_m, t=1.0, U=4.0, V=1.0),
+                                        (E0 - w) + 1j * eta, b[None, :], tol=1e-12, max_iter=20000)
+    assert rc == 0
+    Gm = (Xm[0] @ b).cpu().numpy()
+    wm, wp = float((b.conj() @ b).real), float((bp.conj() @ bp).real)
+    assert abs(wm + wp - 1.0) < 1e-12
+    assert abs(wp - (1 - nu / L)) < 1e-10
+    assert np.all(-Gm.imag >= 0) and np.all(-Gp.imag >= 0)
