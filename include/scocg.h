@@ -204,8 +204,9 @@ int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t 
  *   res     host or NULL: the final ||H psi - E psi||
  *   sweeps  host or NULL: inverse-iteration sweeps done
  * H is a stored matrix or a matrix-free Hubbard operator (the same results bit for bit).
- * Errors: EINVAL (null or bad arguments, nu outside [2, 2^20]), ENOMEM, EHIP, and those of the
- * linear solves.  Synchronous.
+ * Errors: EINVAL (null or bad arguments, nu outside [2, 2^20]), ENOMEM, EHIP, those of the
+ * linear solves, and ENOCONV when the residual norm is still above tol after max_sweeps
+ * sweeps (psi, E, res and sweeps are written).  Synchronous.
  */
 int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double tol, int32_t max_sweeps, double *psi, double *E,
                  double *res, int32_t *sweeps, void *stream);

@@ -1248,6 +1248,7 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     g_timing.total_ms = ms;
     g_timing.iterations = 2 * (int64_t)nu + cg_iters;
     g_timing.blocks = k;
+    if (!(rcur <= tol)) return fail(SCOCG_ENOCONV, "the residual norm is above tol after max_sweeps sweeps");
     return SCOCG_OK;
 }
 

@@ -159,3 +159,28 @@ def test_affinity_spectrum_and_the_total_sum_rule():
     assert abs(wm + wp - 1.0) < 1e-12
     assert abs(wp - (1 - nu / L)) < 1e-10
     assert np.all(-Gm.imag >= 0) and np.all(-Gp.imag >= 0)
+
+
+def test_ground_state_limits_and_bad_arguments():
+    """No sweep allowed and a tolerance the short estimate cannot meet: ENOCONV, with the
+    estimate still returned when asked for; invalid arguments of both calls are rejected."""
+    from paper_0802_0748_amd._capi import ScocgError
+
+    S = _S()
+    L, nu, nd = 8, 4, 4
+    H = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    x0 = np.random.default_rng(3).normal(size=H.n)
+    with pytest.raises(ScocgError):
+        S.ground_state(H, x0, nu=6, tol=1e-12, max_sweeps=0)
+    psi, E0, E1, res, sweeps = S.ground_state(H, x0, nu=6, tol=1e-12, max_sweeps=0, allow_noconv=True)
+    assert sweeps == 0 and res > 1e-12 and np.isfinite(E0)
+    assert abs(float((psi.conj() @ psi).real) - 1.0) < 1e-12
+    for bad in [dict(nu=1), dict(nu=(1 << 20) + 1), dict(tol=0.0), dict(max_sweeps=-1)]:
+        with pytest.raises(ScocgError):
+            S.ground_state(H, x0, **bad)
+    x = torch.from_numpy(_crand(H.n, 1)).cuda()
+    for site, spin in [(-1, 0), (L, 0), (0, 2)]:
+        with pytest.raises(ScocgError):
+            S.hubbard_fermion_op(L, nu, nd, site, spin, False, x)
+    with pytest.raises(ValueError):  # no sector with nine up electrons on eight sites
+        S.hubbard_fermion_op(L, L, nd, 0, 0, True, torch.zeros(70, dtype=torch.complex128, device="cuda"))
