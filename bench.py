@@ -336,11 +336,41 @@ def cpu_baseline(p, gpu_iters, sample_iters, row_scale=None, converged=None):
     if converged is None:
         converged = gpu_iters.size
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same sample on one thread, in a child process (the oracle's thread count is fixed
+    # when it loads), a twentieth of the iterations
+    single = None
+    n1 = max(1, sample_iters // 20)
+    code = ("import sys, time, numpy as np; sys.path.insert(0, sys.argv[1]); from oracle import oracle as O; "
+            "from workloads import config1_cubic, config2_diamond, config3_hubbard; "
+            "p = {'diamond': config2_diamond, 'cubic': config1_cubic}[sys.argv[2]](n_shift=int(sys.argv[3])); "
+            "b = p.rhs_dense()[0]; O.shifted_cocg(p.H, p.z[:1], b, fixed_iter=2); n = int(sys.argv[4]); "
+            "t0 = time.perf_counter(); O.shifted_cocg(p.H, p.z, b, fixed_iter=n, seed_index=0); "
+            "t1 = time.perf_counter(); O.shifted_cocg(p.H, p.z[:1], b, fixed_iter=n, seed_index=0); "
+            "print(t1 - t0, time.perf_counter() - t1)")
+    wl = next((w for w in ("diamond", "cubic") if p.name.startswith(w)), None)
+    if wl is not None and row_scale is None:
+        import subprocess
+
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code, ROOT, wl, str(M), str(n1)], env=env, capture_output=True,
+                           text=True, timeout=600)
+        if r.returncode == 0:
+            a1, o1 = (float(v) for v in r.stdout.split())
+            c1_seed, c1_pair = o1 / n1, max(a1 - o1, 0.0) / ((M - 1) * n1)
+            est1 = float(np.sum(c1_seed * gpu_iters.max(axis=1) + c1_pair * gpu_iters.sum(axis=1)))
+            single = dict(value=converged / est1, cores=1, sample=f"{n1} iterations ({a1:.1f} s, one shift {o1:.1f} s)")
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=converged / est, unit="solves/s", cores=threads, kind="oracle",
                 sample=(f"oracle on the first rhs with all {M} shifts for {sample_iters} fixed iterations "
                         f"({t_all:.1f} s) and with one shift ({t_one:.1f} s); per-pair and per-seed iteration "
                         f"costs scaled by the GPU solve's iteration counts (sum {int(gpu_iters.sum())} pair-"
-                        f"iterations, {int(seed_iters)} seed iterations) to an estimated {est:.3g} s"))
+                        f"iterations, {int(seed_iters)} seed iterations) to an estimated {est:.3g} s"),
+                single_thread=single, cpu_model=cpu_model, nproc=os.cpu_count())
 
 
 def load_workload(args):
