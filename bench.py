@@ -95,9 +95,10 @@ def update_kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, config=None, precision="fp64"):
     """HBM bytes per launch of the update kernel from the committed rocprofv3 counter
-    summary, if it was taken on this workload and the current kernel source (else None)."""
+    summary, if it was taken on this workload, configuration and storage precision (the
+    kernel instance it names) and on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", f"k_flush_{workload}_traffic.json")
     try:
         with open(path) as f:
@@ -106,6 +107,10 @@ def measured_traffic(workload):
     except (OSError, ValueError):
         return None
     if rec.get("kernel_sources_sha1") != digest:
+        return None
+    if config is not None and rec.get("workload") != config:
+        return None
+    if ("double" in rec.get("kernel", "")) != (precision == "fp64"):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -397,7 +402,7 @@ def load_workload(args):
     return p, desc
 
 
-def update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, workload, precision):
+def update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, workload, precision, config=None):
     """Roofline of the deferred per-shift update from its device-counted algorithmic bytes and
     flops over its summed launch time.  Its arithmetic intensity is about T * 16 flops per 64 B
     of x_k, u_k (FP64, T steps per block); above the machine balance (FP64 vector peak over
@@ -412,7 +417,7 @@ def update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, workload, precis
            "bytes_per_launch": upd_bytes / max(upd_launches, 1), "flops_per_launch": upd_flops / max(upd_launches, 1),
            "intensity_flop_per_byte": intensity, "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
            "alu_achieved_tflops": tfs, "alu_frac": tfs / alu_peak}
-    traffic = measured_traffic(workload)
+    traffic = measured_traffic(workload, config, precision)
     if intensity > alu_peak * 1e3 / HBM_PEAK_GBS:
         return {"bound": "alu", "achieved": tfs, "peak": alu_peak, "unit": "TFLOP/s", "frac": tfs / alu_peak,
                 "traffic": traffic, **per}
@@ -683,7 +688,7 @@ def bench_batch(args, S, torch):
                    "n": int(sum(p.H.n for p in probs)), "nnz": int(sum(p.H.nnz for p in probs)), "n_shift": M,
                    "n_rhs": K, "precision": prec, "block": args.block or 48,
                    "iterations_per_step": int(np.max(iters))},
-        "roofline": update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, "batch", prec),
+        "roofline": update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, "batch", prec, ""),
     }
     if not args.no_cpu_baseline:
         p0 = probs[0]
@@ -830,6 +835,8 @@ def main():
     elapsed = time.perf_counter() - t0
     S.set_profiling(False)
     value = converged / elapsed
+    wl_desc = (f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}"
+               + (f", full directions for {args.window} seed candidates" if args.window else ""))
     line = {
         "metric": METRIC,
         "value": value,
@@ -843,11 +850,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-storage/f64-scalars",
         "data": "synthetic",
-        "config": {"workload": f"{desc}, tol {p.tol:g}, max_iter {p.max_iter}"
-                               + (f", full directions for {args.window} seed candidates" if args.window else ""),
+        "config": {"workload": wl_desc,
                    "n": n, "nnz": int(p.H.nnz), "n_shift": M, "n_rhs": K, "precision": args.precision,
                    "block": args.block or 48, "schedule": args.schedule, "iterations_per_step": int(np.max(iters))},
-        "roofline": update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, args.workload, args.precision),
+        "roofline": update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, args.workload, args.precision,
+                                    wl_desc if (args.block in (0, 48) and not args.shifts_per_wg) else ""),
         "hot_path": hot_path(upd_bytes, seed_iters, n, elapsed, 0 if args.matrix_free else 12 * int(p.H.nnz),
                              args.steps * int(np.max(iters))),
     }
