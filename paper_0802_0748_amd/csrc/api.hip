@@ -1209,6 +1209,9 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
         o.max_iter = 1000000;
         o.seed_index = 0;
         o.seed_switching = 0;
+        // one shift: long blocks buy nothing here, and the residual ring (2 T + 1 vectors)
+        // grows with the block length (the iterates are the same for every length)
+        o.block = 4;
         const double zs[2] = {sigma, 0.0};
         SolveRequest rq{};
         rq.H = H;

@@ -105,3 +105,33 @@ def test_diamond_fp32_storage_error_is_stated_per_result():
           flush=True)
     assert np.all(diff <= bound * (1 + 1e-6))
     assert np.max(diff / norm) < 1e-4
+
+
+def test_ground_state_at_the_papers_dimension():
+    """A ring of 16 sites with 6 + 6 electrons has the 64,128,064-state sector of the paper's
+    many-electron problem (Sec. 4.2, tests/golden/sector_dimension_sec4_2.txt).  With U = V = 0
+    its ground energy has a closed form, twice the sum of the 6 lowest periodic levels
+    -2t cos(2 pi m / 16): the matrix-free operator, 120 steps of the recurrence and CG inverse
+    iteration reach it within 1e-9."""
+    import os
+
+    S = _S()
+    gold = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sector_dimension_sec4_2.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                gold[k] = int(v)
+    L, ne = gold["modes_per_spin"], gold["electrons_per_spin"]
+    H = S.Hamiltonian.hubbard(L, ne, ne, t=1.0, U=0.0, V=0.0)
+    assert H.n == gold["dimension"]
+    levels = np.sort(-2.0 * np.cos(2 * np.pi * np.arange(L) / L))
+    exact = 2 * levels[:ne].sum()
+    x0 = np.random.default_rng(16).normal(size=H.n)
+    t0 = time.perf_counter()
+    psi, E0, E1, res, sweeps = S.ground_state(H, x0, nu=120, tol=1e-8, max_sweeps=20)
+    torch.cuda.synchronize()
+    print(f"n={H.n}: E0 {E0:.12f} (closed form {exact:.12f}), residual {res:.1e}, sweeps {sweeps}, "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
+    assert res <= 1e-8
+    assert abs(E0 - exact) < 1e-9

@@ -95,3 +95,25 @@ def test_free_ring_ground_state_closed_form(L, nu, nd):
 
     assert abs(E0 - (fill(nu) + fill(nd))) < 1e-12
     assert abs(np.linalg.norm(psi) - 1.0) < 1e-14
+
+
+def _golden(name):
+    import os
+
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = int(v)
+    return vals
+
+
+def test_sector_dimension_of_the_papers_many_electron_problem():
+    """The S_z = 0 sector size that Sec. 4.2 states for its many-electron problem, from the
+    reference's basis enumeration (16 modes per spin, 6 electrons per spin)."""
+    g = _golden("sector_dimension_sec4_2.txt")
+    up = MB.basis(g["modes_per_spin"], g["electrons_per_spin"])
+    assert len(up) ** 2 == g["dimension"]
+    assert np.all(np.diff(up) > 0)  # increasing patterns, each with 6 bits set
+    assert all(bin(int(s)).count("1") == g["electrons_per_spin"] for s in up[:: max(1, len(up) // 97)])
