@@ -121,6 +121,25 @@ def measured_traffic(workload, config=None, precision="fp64"):
 COPY_BYTES = 2 ** 31
 
 
+def copy_bandwidth(torch, reps=10):
+    """Achievable HBM bandwidth: a device-to-device copy of 2 GiB (read + write counted), best
+    of `reps` timed with events on the current stream."""
+    x = torch.ones(COPY_BYTES // 16, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * COPY_BYTES / best / 1e9
+
+
 def copy_calibration():
     """One device-to-device copy of 2 GiB: the HBM byte counters read on it give the factor
     from counter units to bytes."""
@@ -881,6 +900,14 @@ def main():
         "hot_path": hot_path(upd_bytes, seed_iters, n, elapsed, 0 if args.matrix_free else 12 * int(p.H.nnz),
                              args.steps * int(np.max(iters))),
     }
+    # achievable HBM bandwidth beside the 8 TB/s peak, measured after the timed region
+    copy_gbs = copy_bandwidth(torch)
+    line["hbm_copy"] = {"gbs": copy_gbs, "note": "device-to-device copy of 2 GiB, read + write counted"}
+    line["hot_path"]["frac_of_copy"] = line["hot_path"]["achieved"] / copy_gbs
+    if line["roofline"]["bound"] == "hbm":
+        line["roofline"]["frac_of_copy"] = line["roofline"]["achieved"] / copy_gbs
+    else:
+        line["roofline"]["hbm_frac_of_copy"] = line["roofline"]["hbm_achieved_gbs"] / copy_gbs
     if not args.no_cpu_baseline:
         # the oracle's cost per iteration grows with shifts x rows: keep the sample near
         # --cpu-iters iterations of the diamond problem (256 x 16384)
