@@ -1065,6 +1065,7 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
     s.ell_val = H->d.d_ell_val;
     s.n = n;
     s.K = Kp;
+    s.rb = LZ_RB;
     s.nblk = nblk;
     s.nu = nu;
     s.V[0] = bV0.as<double>();
@@ -1117,14 +1118,15 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     auto A = [&](DevBuf &b, size_t bytes) {
         if (e == hipSuccess) e = b.alloc(bytes);
     };
+    // the recurrence of one plain vector (no interleaved group)
     A(bxs, n * sizeof(double));
-    for (DevBuf *b : {&bV0, &bV1, &bW0, &bW1}) A(*b, (size_t)LZ_RB * n * sizeof(double));
-    A(bpart, (size_t)LZ_RB * 2 * nblk * sizeof(double));
-    A(bab, (size_t)LZ_RB * 2 * nu * sizeof(double));
-    A(bst, LZ_RB * sizeof(LzRhs));
-    A(beig, LZ_RB * 2 * sizeof(double));
-    A(bu, (size_t)LZ_RB * nu * sizeof(double));
-    A(bscr, (size_t)LZ_RB * nu * sizeof(double));
+    for (DevBuf *b : {&bV0, &bV1, &bW0, &bW1}) A(*b, (size_t)n * sizeof(double));
+    A(bpart, (size_t)2 * nblk * sizeof(double));
+    A(bab, (size_t)2 * nu * sizeof(double));
+    A(bst, sizeof(LzRhs));
+    A(beig, 2 * sizeof(double));
+    A(bu, (size_t)nu * sizeof(double));
+    A(bscr, (size_t)nu * sizeof(double));
     A(bacc, n * sizeof(double));
     A(by, 2 * n * sizeof(double));
     A(bscal, 8 * sizeof(double));
@@ -1144,13 +1146,9 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     double *xs = bxs.as<double>();
     HIPCHK(hipMemcpyAsync(xs, x0, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(sv_normalize(v, xs, nullptr, st));
-    // one right-hand side in a group of LZ_RB (the others finished from the start)
-    std::vector<LzRhs> hst(LZ_RB);
-    for (int c = 0; c < LZ_RB; ++c) {
-        hst[c] = LzRhs{};
-        hst[c].j = -1;
-        hst[c].done = c == 0 ? 0 : 1;
-    }
+    std::vector<LzRhs> hst(1);
+    hst[0] = LzRhs{};
+    hst[0].j = -1;
     LzDev s{};
     s.hub = v.hub;
     s.slice_ptr = v.slice_ptr;
@@ -1158,7 +1156,8 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     s.ell_col = v.ell_col;
     s.ell_val = v.ell_val;
     s.n = n;
-    s.K = LZ_RB;
+    s.K = 1;
+    s.rb = 1;
     s.nblk = nblk;
     s.nu = nu;
     s.V[0] = bV0.as<double>();
@@ -1173,14 +1172,14 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
     HIPCHK(hipEventRecord(t0, st));
-    HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), LZ_RB * sizeof(LzRhs), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), sizeof(LzRhs), hipMemcpyHostToDevice, st));
     for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
     HIPCHK(launch_lanczos_lowest(s, beig.as<double>(), bu.as<double>(), bscr.as<double>(), st));
     double eig[2];
     HIPCHK(hipMemcpyAsync(eig, beig.ptr, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     // the same recurrence again (same bits), summing the Ritz vector sum_n u_n K_n
     HIPCHK(hipMemsetAsync(bacc.ptr, 0, n * sizeof(double), st));
-    HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), LZ_RB * sizeof(LzRhs), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), sizeof(LzRhs), hipMemcpyHostToDevice, st));
     s.acc = bacc.as<double>();
     s.coef = bu.as<double>();
     for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));

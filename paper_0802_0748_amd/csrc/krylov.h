@@ -34,10 +34,11 @@ struct LzDev {
     const int32_t *ell_col;
     const double *ell_val;
     int64_t n;
-    int64_t K;     // right-hand sides (padded to groups of LZ_RB with finished entries)
+    int64_t K;     // right-hand sides (padded to groups of rb with finished entries)
     int64_t nblk;  // 256-row tiles, one partial sum each
     int32_t nu;
-    double *V[2];  // basis vectors K_n by parity of n: [K / LZ_RB][n][LZ_RB]
+    int32_t rb;    // right-hand sides interleaved per group: LZ_RB, or 1 (plain vectors)
+    double *V[2];  // basis vectors K_n by parity of n: [K / rb][n][rb]
     double *W[2];  // unnormalized next vectors by parity
     double *part;  // [K][nblk] partial sums
     double *ab;    // [K][2][nu]: a_1..a_m, then b_2..b_{m+1}

@@ -16,22 +16,37 @@ namespace scocg {
 typedef double d4v __attribute__((ext_vector_type(4)));
 static_assert(LZ_TILE == WG, "one 256-row tile per workgroup");
 
-// Tree sums of LZ_RB values over the WG threads (result in thread 0).
-__device__ inline void block_sum_rb(double (&v)[LZ_RB], double (*sh)[WG])
+// One row of a group of RB interleaved vectors: four doubles (one 32-byte access), or one.
+template <int RB> struct LzRow;
+template <> struct LzRow<4> {
+    typedef d4v T;
+};
+struct LzOne {
+    double v;
+    __device__ double &operator[](int) { return v; }
+    __device__ double operator[](int) const { return v; }
+};
+template <> struct LzRow<1> {
+    typedef LzOne T;
+};
+
+// Tree sums of RB values over the WG threads (result in thread 0).
+template <int RB>
+__device__ inline void block_sum_rb(double (&v)[RB], double (*sh)[WG])
 {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int b = 0; b < LZ_RB; ++b) sh[b][t] = v[b];
+    for (int b = 0; b < RB; ++b) sh[b][t] = v[b];
     __syncthreads();
     for (int h = WG / 2; h > 0; h >>= 1) {
         if (t < h) {
 #pragma unroll
-            for (int b = 0; b < LZ_RB; ++b) sh[b][t] += sh[b][t + h];
+            for (int b = 0; b < RB; ++b) sh[b][t] += sh[b][t + h];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int b = 0; b < LZ_RB; ++b) v[b] = sh[b][0];
+    for (int b = 0; b < RB; ++b) v[b] = sh[b][0];
 }
 
 // Fixed-order sum of a right-hand side's tile partials by one workgroup (result in thread 0):
@@ -60,17 +75,19 @@ __device__ inline double sum_tiles(const double *part, int64_t nblk, double *sh)
 
 // w = H K_n - b_n K_{n-1} and the partials of K_n . w; K_n (= the previous w times 1/b_n, or
 // the unit vector at step 0) is written out for the step after.
+template <int RB>
 __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
 {
-    __shared__ double sh[LZ_RB][WG];
+    typedef typename LzRow<RB>::T VR;
+    __shared__ double sh[RB][WG];
     const int64_t g = blockIdx.y;
-    bool run[LZ_RB];
-    double bprev[LZ_RB], rb[LZ_RB];
-    int64_t jj[LZ_RB];
+    bool run[RB];
+    double bprev[RB], rb[RB];
+    int64_t jj[RB];
     bool any = false;
 #pragma unroll
-    for (int b = 0; b < LZ_RB; ++b) {
-        const LzRhs st = s.st[g * LZ_RB + b];
+    for (int b = 0; b < RB; ++b) {
+        const LzRhs st = s.st[g * RB + b];
         run[b] = !st.done;
         bprev[b] = run[b] ? st.bprev : 0.0;
         rb[b] = (run[b] && n > 0) ? 1.0 / st.bprev : 0.0;
@@ -80,30 +97,30 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
     if (!any) return;  // uniform over the workgroup
     const int q = n & 1;
     const int64_t base = g * s.n;
-    const d4v *Wp = (const d4v *)(s.W[q ^ 1]) + base;
-    const d4v *Vp = (const d4v *)(s.V[q ^ 1]) + base;
-    d4v *Vn = (d4v *)(s.V[q]) + base;
-    d4v *Wn = (d4v *)(s.W[q]) + base;
+    const VR *Wp = (const VR *)(s.W[q ^ 1]) + base;
+    const VR *Vp = (const VR *)(s.V[q ^ 1]) + base;
+    VR *Vn = (VR *)(s.V[q]) + base;
+    VR *Wn = (VR *)(s.W[q]) + base;
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
-    double dot[LZ_RB] = {0, 0, 0, 0};
+    double dot[RB] = {};
     if (row < s.n) {
-        double acc[LZ_RB] = {0, 0, 0, 0};
+        double acc[RB] = {};
         // one term of the row: acc += v x[c]
         auto slot = [&](int64_t c, double v) {
-            double x[LZ_RB];
+            double x[RB];
             if (n == 0 && s.x0) {
 #pragma unroll
-                for (int b = 0; b < LZ_RB; ++b) x[b] = run[b] ? s.x0[(g * LZ_RB + b) * s.n + c] : 0.0;
+                for (int b = 0; b < RB; ++b) x[b] = run[b] ? s.x0[(g * RB + b) * s.n + c] : 0.0;
             } else if (n == 0) {
 #pragma unroll
-                for (int b = 0; b < LZ_RB; ++b) x[b] = (c == jj[b]) ? 1.0 : 0.0;
+                for (int b = 0; b < RB; ++b) x[b] = (c == jj[b]) ? 1.0 : 0.0;
             } else {
-                const d4v wc = Wp[c];
+                const VR wc = Wp[c];
 #pragma unroll
-                for (int b = 0; b < LZ_RB; ++b) x[b] = wc[b] * rb[b];
+                for (int b = 0; b < RB; ++b) x[b] = wc[b] * rb[b];
             }
 #pragma unroll
-            for (int b = 0; b < LZ_RB; ++b) acc[b] = fma(v, x[b], acc[b]);
+            for (int b = 0; b < RB; ++b) acc[b] = fma(v, x[b], acc[b]);
         };
         if (s.hub) {
             // the operator's terms in the stored row's column order: the same sums
@@ -132,17 +149,17 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
             }
             for (; k < w; ++k) slot(colp[(int64_t)k * 64], valp[(int64_t)k * 64]);
         }
-        d4v vo, wo;
+        VR vo, wo;
         if (n == 0) {
 #pragma unroll
-            for (int b = 0; b < LZ_RB; ++b) {
-                vo[b] = s.x0 ? (run[b] ? s.x0[(g * LZ_RB + b) * s.n + row] : 0.0) : ((row == jj[b]) ? 1.0 : 0.0);
+            for (int b = 0; b < RB; ++b) {
+                vo[b] = s.x0 ? (run[b] ? s.x0[(g * RB + b) * s.n + row] : 0.0) : ((row == jj[b]) ? 1.0 : 0.0);
                 wo[b] = acc[b];
             }
         } else {
-            const d4v wr = Wp[row], vr = Vp[row];
+            const VR wr = Wp[row], vr = Vp[row];
 #pragma unroll
-            for (int b = 0; b < LZ_RB; ++b) {
+            for (int b = 0; b < RB; ++b) {
                 vo[b] = wr[b] * rb[b];
                 wo[b] = fma(-bprev[b], vr[b], acc[b]);
             }
@@ -151,20 +168,20 @@ __global__ void __launch_bounds__(WG) k_lz_matvec(LzDev s, int n)
         Wn[row] = wo;
         if (s.acc) {
 #pragma unroll
-            for (int b = 0; b < LZ_RB; ++b)
+            for (int b = 0; b < RB; ++b)
                 if (run[b]) {
-                    const int64_t k = g * LZ_RB + b;
+                    const int64_t k = g * RB + b;
                     s.acc[k * s.n + row] = fma(s.coef[k * s.nu + n], vo[b], s.acc[k * s.n + row]);
                 }
         }
 #pragma unroll
-        for (int b = 0; b < LZ_RB; ++b) dot[b] = vo[b] * wo[b];
+        for (int b = 0; b < RB; ++b) dot[b] = vo[b] * wo[b];
     }
-    block_sum_rb(dot, sh);
+    block_sum_rb<RB>(dot, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int b = 0; b < LZ_RB; ++b)
-            if (run[b]) s.part[(g * LZ_RB + b) * s.nblk + blockIdx.x] = dot[b];
+        for (int b = 0; b < RB; ++b)
+            if (run[b]) s.part[(g * RB + b) * s.nblk + blockIdx.x] = dot[b];
     }
 }
 
@@ -182,16 +199,18 @@ __global__ void __launch_bounds__(WG) k_lz_alpha(LzDev s, int n)
 }
 
 // w <- w - a_n K_n and the partials of ||w||^2
+template <int RB>
 __global__ void __launch_bounds__(WG) k_lz_axpy(LzDev s, int n)
 {
-    __shared__ double sh[LZ_RB][WG];
+    typedef typename LzRow<RB>::T VR;
+    __shared__ double sh[RB][WG];
     const int64_t g = blockIdx.y;
-    bool run[LZ_RB];
-    double a[LZ_RB];
+    bool run[RB];
+    double a[RB];
     bool any = false;
 #pragma unroll
-    for (int b = 0; b < LZ_RB; ++b) {
-        const LzRhs st = s.st[g * LZ_RB + b];
+    for (int b = 0; b < RB; ++b) {
+        const LzRhs st = s.st[g * RB + b];
         run[b] = !st.done;
         a[b] = run[b] ? st.a : 0.0;
         any = any || run[b];
@@ -199,25 +218,25 @@ __global__ void __launch_bounds__(WG) k_lz_axpy(LzDev s, int n)
     if (!any) return;
     const int q = n & 1;
     const int64_t base = g * s.n;
-    const d4v *Vn = (const d4v *)(s.V[q]) + base;
-    d4v *Wn = (d4v *)(s.W[q]) + base;
+    const VR *Vn = (const VR *)(s.V[q]) + base;
+    VR *Wn = (VR *)(s.W[q]) + base;
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
-    double nn[LZ_RB] = {0, 0, 0, 0};
+    double nn[RB] = {};
     if (row < s.n) {
-        const d4v v = Vn[row];
-        d4v w = Wn[row];
+        const VR v = Vn[row];
+        VR w = Wn[row];
 #pragma unroll
-        for (int b = 0; b < LZ_RB; ++b) {
+        for (int b = 0; b < RB; ++b) {
             w[b] = fma(-a[b], v[b], w[b]);
             nn[b] = w[b] * w[b];
         }
         Wn[row] = w;
     }
-    block_sum_rb(nn, sh);
+    block_sum_rb<RB>(nn, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int b = 0; b < LZ_RB; ++b)
-            if (run[b]) s.part[(g * LZ_RB + b) * s.nblk + blockIdx.x] = nn[b];
+        for (int b = 0; b < RB; ++b)
+            if (run[b]) s.part[(g * RB + b) * s.nblk + blockIdx.x] = nn[b];
     }
 }
 
@@ -481,12 +500,15 @@ __global__ void k_fermion_op(const uint32_t *__restrict__ up, const uint32_t *__
 
 hipError_t launch_lanczos_step(const LzDev &s, int n, hipStream_t st)
 {
-    const int64_t groups = s.K / LZ_RB;
+    if (s.rb != 1 && s.rb != LZ_RB) return hipErrorInvalidValue;
+    const int64_t groups = s.K / s.rb;
     if (s.nblk > 0x7fffffffLL || groups > 65535 || s.K > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const dim3 gv((unsigned)s.nblk, (unsigned)groups);
-    hipLaunchKernelGGL(k_lz_matvec, gv, dim3(WG), 0, st, s, n);
+    if (s.rb == 1) hipLaunchKernelGGL(k_lz_matvec<1>, gv, dim3(WG), 0, st, s, n);
+    else hipLaunchKernelGGL(k_lz_matvec<LZ_RB>, gv, dim3(WG), 0, st, s, n);
     hipLaunchKernelGGL(k_lz_alpha, dim3((unsigned)s.K), dim3(WG), 0, st, s, n);
-    hipLaunchKernelGGL(k_lz_axpy, gv, dim3(WG), 0, st, s, n);
+    if (s.rb == 1) hipLaunchKernelGGL(k_lz_axpy<1>, gv, dim3(WG), 0, st, s, n);
+    else hipLaunchKernelGGL(k_lz_axpy<LZ_RB>, gv, dim3(WG), 0, st, s, n);
     hipLaunchKernelGGL(k_lz_beta, dim3((unsigned)s.K), dim3(WG), 0, st, s, n);
     return hipGetLastError();
 }
