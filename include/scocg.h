@@ -227,6 +227,27 @@ int hubbard_fermion_op(int32_t L, int32_t n_up, int32_t n_dn, int32_t site, int3
                        const double *x, double *y, void *stream);
 
 /*
+ * Projected Green's functions G[k][j] = <w_j|(z_k - H)^{-1}|b_j> = sum_i w_j[i] x_{j,k}[i]
+ * (bilinear; for real w_j it is the matrix element the spectra of Sec. 4.2 need) for dense
+ * right-hand sides b_j and projection vectors w_j, in the regime Sec. 3.3 describes: when only
+ * a projection of each solution is wanted, every shifted system is carried by scalars.  One
+ * reduction per seed iteration gives s_n = w_j . r_n, and each pair's <w|x_k>, <w|u_k> follow
+ * the deferred update's steps with s_n in place of the residual; full directions u_k are kept
+ * only for o->window seed candidates (all shifts when window = 0), which a seed switch needs.
+ * As in greens_diag's window mode, a seed switch goes to the active stored shift with the
+ * largest residual, and when none is left the pairs still active stop unconverged.
+ *   H       stored matrix or matrix-free operator
+ *   B, W    device, [n_rhs][n] complex each (W = B for <b|G|b>)
+ *   G       device, [n_shift][n_rhs] complex output
+ *   rep     host, [n_rhs][n_shift] reports, or NULL (rel_res_true is -1: no solutions are kept)
+ * Device memory: n_shift * n_rhs scalars plus window (or n_shift) direction vectors of n
+ * complex numbers per right-hand side.  Errors: EINVAL (null or bad arguments), ENOMEM,
+ * EHIP, EBREAKDOWN, ENOCONV (results still written).
+ */
+int greens_proj(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const double *B, const double *W,
+                const scocg_opts *o, double *G, scocg_pair_report *rep, void *stream);
+
+/*
  * G_jj(z_k) for several Hamiltonians of different sizes in one solve (a batch of
  * independent problems sharing the shift list).  Problem q has n_rhs[q] unit
  * right-hand sides; rhs_idx lists them problem after problem (indices local to the

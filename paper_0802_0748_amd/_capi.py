@@ -69,6 +69,7 @@ EXPORTED = [
     "shifted_cocg_solve",
     "greens_diag",
     "greens_diag_batched",
+    "greens_proj",
     "krylov_greens_diag",
     "ground_state",
     "hubbard_fermion_op",
@@ -124,6 +125,8 @@ def load():
     lib.greens_diag.restype = i32
     lib.greens_diag_batched.argtypes = [i64, P, P, P, i64, P, ctypes.POINTER(Opts), P, P, P]
     lib.greens_diag_batched.restype = i32
+    lib.greens_proj.argtypes = [P, i64, P, i64, P, P, ctypes.POINTER(Opts), P, P, P]
+    lib.greens_proj.restype = i32
     lib.density_matrix_energy.argtypes = [P, i64, P, P, i64, P, ctypes.POINTER(Opts), i64, P, P, P, P]
     lib.density_matrix_energy.restype = i32
     lib.backward.argtypes = [P, P, P, P]

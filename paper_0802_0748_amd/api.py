@@ -273,6 +273,28 @@ def hubbard_fermion_op(L: int, n_up: int, n_dn: int, site: int, spin: int, creat
     return y, (tu, td)
 
 
+def greens_proj(H: Hamiltonian, z, B: torch.Tensor, W: torch.Tensor = None, allow_noconv=True, allow_breakdown=False,
+                **opts):
+    """<w_j|(z_k - H)^{-1}|b_j> (bilinear) for the rows b_j of B and w_j of W (default W = B),
+    every shift carried by scalars; full directions only for `window` seed candidates.
+    Returns (G [n_shift, n_rhs] complex128, report dict, timing dict, status)."""
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    B = B.to(torch.complex128).contiguous()
+    W = B if W is None else W.to(torch.complex128).contiguous()
+    if B.dim() != 2 or B.shape[1] != H.n or W.shape != B.shape:
+        raise ValueError("B and W must be [n_rhs, n] complex")
+    K, M = B.shape[0], len(zh)
+    o = options(**opts)
+    G = torch.empty((M, K), dtype=torch.complex128, device=B.device)
+    rep = (C.PairReport * (K * M))()
+    rc = lib.greens_proj(H.handle, M, zp, K, B.data_ptr(), W.data_ptr(), ctypes.byref(o), G.data_ptr(), rep,
+                         _stream_ptr())
+    C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
+    return G, _report(rep, K, M), last_timing(), rc
+
+
 def greens_diag_batched(Hs, z, rhs_lists, allow_noconv=True, allow_breakdown=False, **opts):
     """G_jj(z_k) for several Hamiltonians of different sizes in one solve.
 

@@ -452,6 +452,7 @@ struct SolveRequest {
     scocg_pair_report *rep;
     DevBuf *keepX;            // receives the full FP64 solutions (tape) or null
     bool zper;                // z has one shift per rhs (n_shift = 1): used by the refinement solves
+    const double2 *wproj;     // device [K][n] projection weights (projection mode: G = <w|x>), or null
 };
 
 int solve(SolveRequest &rq, hipStream_t st)
@@ -510,6 +511,8 @@ int solve(SolveRequest &rq, hipStream_t st)
     const bool need_full = !rq.projection;
     if (o.window < 0) return fail(SCOCG_EINVAL, "window must be >= 0");
     if (o.window > 0 && need_full) return fail(SCOCG_EINVAL, "window needs projection mode (greens_diag without tape)");
+    if (rq.wproj && (need_full || !rq.B || !rq.Hj.empty()))
+        return fail(SCOCG_EINVAL, "a vector projection needs projection mode, dense right-hand sides and one matrix");
     // window of seed candidates: the only shifts whose full directions are stored
     const int64_t Mst = (o.window > 0 && o.window < M) ? o.window : M;
     std::vector<int32_t> h_wshift, h_wslot;
@@ -605,7 +608,12 @@ int solve(SolveRequest &rq, hipStream_t st)
     if (Mst < M) {
         ALLOC(bwshift, (size_t)K * Mst * sizeof(int32_t));
         ALLOC(bwslot, KM * sizeof(int32_t));
-        ALLOC(bUproj, KM * sizeof(double2));
+    }
+    if (Mst < M || rq.wproj) ALLOC(bUproj, KM * sizeof(double2));
+    DevBuf bshist, bpart3;
+    if (rq.wproj) {
+        ALLOC(bshist, (size_t)K * TB * sizeof(double2));
+        ALLOC(bpart3, (size_t)K * s.nblk * sizeof(double2));
     }
     const bool x_is_out = need_full && o.precision == 0 && rq.Xout && !rq.keepX;
     if (need_full && !x_is_out) ALLOC(bX, (size_t)M * ntot * esz);
@@ -646,7 +654,10 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.Mst = Mst;
     s.wshift = Mst < M ? bwshift.as<int32_t>() : nullptr;
     s.wslot = Mst < M ? bwslot.as<int32_t>() : nullptr;
-    s.Uproj = Mst < M ? bUproj.as<double2>() : nullptr;
+    s.Uproj = (Mst < M || rq.wproj) ? bUproj.as<double2>() : nullptr;
+    s.wproj = rq.wproj;
+    s.shist = rq.wproj ? bshist.as<double2>() : nullptr;
+    s.part3 = rq.wproj ? bpart3.as<double2>() : nullptr;
     s.X = need_full ? (x_is_out ? (void *)rq.Xout : bX.ptr) : nullptr;
     s.Xproj = need_full ? nullptr : bXproj.as<double2>();
     s.proj_row = need_full ? nullptr : bprow.as<int64_t>();
@@ -679,6 +690,12 @@ int solve(SolveRequest &rq, hipStream_t st)
     if (rq.unit_idx) {
         HIPCHK(hipMemcpyAsync(bidx.ptr, rq.unit_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
         if (!need_full) HIPCHK(hipMemcpyAsync(bprow.ptr, rq.unit_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    std::vector<int64_t> no_row;
+    if (rq.wproj) {
+        // no kept row: every pair's projection is carried by scalars
+        no_row.assign(K, -1);
+        HIPCHK(hipMemcpyAsync(bprow.ptr, no_row.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, st));
     }
     HIPCHK(launch_zero(bcnt.ptr, K * sizeof(uint32_t), st));
     HIPCHK(launch_zero(bnact.ptr, 2 * KM * sizeof(int32_t), st));
@@ -851,7 +868,7 @@ int solve(SolveRequest &rq, hipStream_t st)
             else if (rq.keepX) g.X = rq.keepX->ptr;
             else return fail(SCOCG_EINVAL, "FP32 greens_diag needs projection mode");
         }
-        HIPCHK(launch_gather_diag(g, bidx.as<int64_t>(), rq.Gout, st));
+        HIPCHK(launch_gather_diag(g, rq.unit_idx ? bidx.as<int64_t>() : nullptr, rq.Gout, st));
     }
     HIPCHK(hipEventRecord(ev_t1, st));
 
@@ -1330,6 +1347,29 @@ extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int6
         }
     }
     return rc;
+}
+
+// <w_j|(z_k - H)^{-1}|b_j> for dense right-hand sides b_j and projection vectors w_j (Sec. 3.3:
+// when only a projection of the solution is wanted, each shifted system costs scalar work).
+extern "C" int greens_proj(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const double *B,
+                           const double *W, const scocg_opts *o, double *G, scocg_pair_report *rep, void *stream)
+{
+    g_err.clear();
+    if (!H || !z || !B || !W || !o || !G) return fail(SCOCG_EINVAL, "null argument");
+    SolveRequest rq{};
+    rq.H = H;
+    rq.M = n_shift;
+    rq.K = n_rhs;
+    rq.z = z;
+    rq.B = (const double2 *)B;
+    rq.unit_idx = nullptr;
+    rq.o = *o;
+    rq.Xout = nullptr;
+    rq.projection = true;
+    rq.Gout = (double2 *)G;
+    rq.rep = rep;
+    rq.wproj = (const double2 *)W;
+    return solve(rq, (hipStream_t)stream);
 }
 
 extern "C" int greens_diag_batched(int64_t n_problems, const scocg_csr_t *H, const int64_t *n_rhs,

@@ -265,6 +265,35 @@ __global__ void __launch_bounds__(WG) k_pupd(SolveDev s)
     if (!any) return;
     const RhsDesc d = s.desc[j0];
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (s.wproj) {
+        // vector projection: also the partials of s_n = w . r_n (bilinear), one per 256 rows
+        __shared__ double2 sh2[WG];
+        if ((int64_t)blockIdx.x * WG >= d.n) return;  // uniform: past this rhs's rows
+        double2 wr[RB];
+        if (row < d.n) {
+            double2 *p = s.p + p_index(s, j0, d, row);
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                wr[b] = cmk(0, 0);
+                if (run[b]) {
+                    const RhsDesc db = s.desc[j0 + b];
+                    const double2 r = ring_slot(s, (st[b].base + st[b].step) % s.R, db)[row];
+                    p[b] = cfma(st[b].beta_prev, p[b], r);
+                    wr[b] = cmul(s.wproj[db.voff + row], r);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) wr[b] = cmk(0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            if (!run[b]) continue;  // uniform across the workgroup
+            const double2 v = block_sum2(wr[b], sh2);
+            if (threadIdx.x == 0) s.part3[(j0 + b) * s.nblk + blockIdx.x] = v;
+        }
+        return;
+    }
     if (row >= d.n) return;
     double2 *p = s.p + p_index(s, j0, d, row);
     double2 pv[RB];
@@ -648,6 +677,10 @@ __global__ void __launch_bounds__(NT) k_alpha(SolveDev s)
     if (!seed_running(st, s.TB)) return;
     if (red_big(s.desc[j]) != (NT == RWG_BIG)) return;
     const double2 tot = sum_partials2<false, NT>(s.part2 + j * s.nblk, nparts(s.desc[j]), sh2);
+    if (s.wproj) {
+        const double2 sn = sum_partials2<false, NT>(s.part3 + j * s.nblk, nparts(s.desc[j]), sh2);
+        if (threadIdx.x == 0) s.shist[j * s.TB + st.step] = sn;
+    }
     if (threadIdx.x == 0) {
         if (cis0(tot) || cis0(st.rho)) s.seed[j].status = SEED_BREAKDOWN;
         else s.ahist[j * s.TB + st.step] = cdiv(st.rho, tot);
@@ -782,7 +815,19 @@ __device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t
     s.active[pair] = act;
     s.nact[pair] = na;
     if (na == 0) return 0ull;
-    if (s.wslot && s.wslot[pair] < 0) {
+    if (s.wproj) {
+        // vector projection: <w|x_k> and <w|u_k> of every pair follow the block's steps with
+        // s_t = w . r_t in place of r_t (the update is linear); a stored direction still
+        // gets its full u_k below, for a seed switch
+        V x = to_v<V>(s.Xproj[pair]), u = to_v<V>(s.Uproj[pair]);
+        for (int t = 0; t < na; ++t) {
+            u = cfma(cf[2 * t + 1], u, to_v<V>(s.shist[j * s.TB + t]));
+            x = cfma(cf[2 * t + 0], u, x);
+        }
+        s.Xproj[pair] = make_double2((double)x.x, (double)x.y);
+        s.Uproj[pair] = make_double2((double)u.x, (double)u.y);
+        if (s.wslot && s.wslot[pair] < 0) return 0ull;
+    } else if (s.wslot && s.wslot[pair] < 0) {
         // no stored direction: carry x_k and u_k at the kept row only, with the same
         // arithmetic the deferred update applies to a stored direction
         const int64_t at = s.desc[j].voff + s.proj_row[j];
@@ -1012,13 +1057,14 @@ __global__ void __launch_bounds__(WG) k_switch_vectors(SolveDev s)
         }
         rr = cmul(r, r);
     }
-    if (s.wslot && blockIdx.x == 0) {
-        // the same rescale for the pairs carried by scalars at the kept row
+    if ((s.wslot || s.wproj) && blockIdx.x == 0) {
+        // the same rescale for the pairs carried by scalars at the kept row (with a vector
+        // projection: the projected u_k of every pair)
         const V sc = to_v<V>(st.inv_ppt);
         const V zero = to_v<V>(cmk(0, 0));
         for (int64_t k = threadIdx.x; k < s.M; k += WG) {
             const int64_t pair = j * s.M + k;
-            if (!s.active[pair] || s.wslot[pair] >= 0) continue;
+            if (!s.active[pair] || (!s.wproj && s.wslot[pair] >= 0)) continue;
             const V u = cfma(sc, to_v<V>(s.Uproj[pair]), zero);
             s.Uproj[pair] = make_double2((double)u.x, (double)u.y);
         }

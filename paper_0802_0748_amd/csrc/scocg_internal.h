@@ -152,6 +152,9 @@ struct SolveDev {
     const int32_t *wslot;      // [K*M] stored-direction slot of each pair or -1, or null (identity)
     double2 *Uproj;            // [K*M] u_k at the kept row for pairs without a stored direction, or null
     double2 *Xproj;            // [K][M] projected solution (projection mode) or null
+    const double2 *wproj;      // [K][n] projection weights w (vector projection: Xproj = <w|x>), or null
+    double2 *shist;            // [K][TB] s_n = w . r_n of the block's steps (vector projection)
+    double2 *part3;            // [K][nblk] partials of w . r_n (vector projection)
     const int64_t *proj_row;   // [K] row kept in projection mode
     double2 *pi, *pi_prev, *beta_k; // [K*M]
     double *res;               // [K*M]

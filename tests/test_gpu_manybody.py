@@ -184,3 +184,43 @@ def test_ground_state_limits_and_bad_arguments():
             S.hubbard_fermion_op(L, nu, nd, site, spin, False, x)
     with pytest.raises(ValueError):  # no sector with nine up electrons on eight sites
         S.hubbard_fermion_op(L, L, nd, 0, 0, True, torch.zeros(70, dtype=torch.complex128, device="cuda"))
+
+
+def test_projected_greens_functions_carried_by_scalars():
+    """greens_proj: <w|(z - H)^{-1}|b> with every shift carried by scalars (Sec. 3.3) for the
+    removal part of the ground state, diagonal (w = b) and off-diagonal (w = c_{1,up}|psi0>),
+    against dense solves of the reference; all shifts stored or a window of four; and in
+    fixed-iteration mode against the full solutions' projections."""
+    S = _S()
+    L, nu, nd = 8, 4, 4
+    Hc = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    H = S.Hamiltonian.hubbard(L, nu, nd, t=1.0, U=4.0, V=1.0)
+    psi, E0, _, _, _ = S.ground_state(H, np.random.default_rng(4).normal(size=Hc.n), nu=120, tol=1e-11)
+    b0, sec = S.hubbard_fermion_op(L, nu, nd, 0, 0, False, psi)
+    b1, _ = S.hubbard_fermion_op(L, nu, nd, 1, 0, False, psi)
+    Hm_dense = hubbard_ring(L, *sec, t=1.0, U=4.0, V=1.0).to_dense()
+    Hm = S.Hamiltonian.hubbard(L, *sec, t=1.0, U=4.0, V=1.0)
+    w = np.linspace(-8, 8, 33)
+    z = (E0 - w) + 0.1j
+    B = torch.stack([b0, b0])
+    Wt = torch.stack([b0, b1])
+    bn, b1n = b0.cpu().numpy(), b1.cpu().numpy()
+    ref = []
+    for zk in z:
+        xk = np.linalg.solve(zk * np.eye(len(bn)) - Hm_dense, bn)
+        ref.append([bn @ xk, b1n @ xk])
+    ref = np.array(ref)
+    for window in (0, 4):
+        G, rep, _, rc = S.greens_proj(Hm, z, B, Wt, tol=1e-12, max_iter=20000, window=window)
+        G = G.cpu().numpy()
+        ok = rep["status"].T == 0  # [shift][rhs]
+        print(f"window {window}: rc {rc}, converged {ok.sum()} of {ok.size}, switches {S.last_timing()['switches']}")
+        if window == 0:
+            assert rc == 0 and ok.all()
+        assert ok.sum() >= ok.size // 2
+        err = np.abs(G - ref) / np.abs(ref).max(axis=0)
+        assert np.max(err[ok]) < 1e-8, (window, np.max(err[ok]))
+    X, _, _, _ = S.shifted_cocg_solve(Hm, z, B[:1], fixed_iter=40, seed_index=3)
+    Gf, _, _, _ = S.greens_proj(Hm, z, B[:1], Wt[:1], fixed_iter=40, seed_index=3)
+    proj = (X[0] @ b0).cpu().numpy()
+    assert np.max(np.abs(Gf.cpu().numpy()[:, 0] - proj) / np.abs(proj)) < 1e-10
