@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--sites", type=int, default=0, help="manybody workload: ring sites (default 14)")
     ap.add_argument("--electrons", type=int, default=0,
                     help="manybody workload: electrons per spin (default half filling)")
+    ap.add_argument("--full-solutions", action="store_true",
+                    help="manybody workload: spectra from full solution vectors instead of projected solves")
     ap.add_argument("--stored-ground-state", action="store_true",
                     help="manybody workload: ground state on the stored sector matrix instead of the operator")
     ap.add_argument("--window", type=int, default=0,
@@ -560,7 +562,7 @@ def bench_manybody(args, S, torch):
     three-term recurrence and CG inverse iteration to ||H psi - E0 psi|| <= 1e-10;
     b = c_{0,up}|psi0> then lies in the 6+7 sector (10,306,296 states, matrix-free operator),
     where shifted COCG gives <b|((E0 - w) + i eta - H)^{-1}|b> at 128 energies w in [-10, 20],
-    eta = 0.05 (removal spectrum); b' = c+_{0,up}|psi0> in the 8+7 sector gives the addition
+    eta = 0.05 (removal spectrum; projected solves, Sec. 3.3); b' = c+_{0,up}|psi0> in the 8+7 sector gives the addition
     spectrum <b'|((E0 + w) + i eta - H)^{-1}|b'> the same way.  The removal weight <b|b> is the
     occupation <n_{0,up}> = N_up / L, and the two weights add up to exactly 1.  --sites and
     --electrons choose another sector (16 sites with 6 + 6 electrons has the 64,128,064 states
@@ -591,10 +593,17 @@ def bench_manybody(args, S, torch):
     M = args.n_shift or 128
     w = np.linspace(-10.0, 20.0, M)
 
+    window = args.window or 32
+
     def spectrum(Hs, bv, z):
-        """<b|(z_k - H)^{-1}|b> for all shifts: one solve, or waves of shifts whose solution and
+        """<b|(z_k - H)^{-1}|b> for all shifts: one projected solve (greens_proj) that carries
+        every shift by scalars and keeps full directions for `window` seed candidates (--window,
+        default 32).  With --full-solutions: full solutions, in one solve or in waves of shifts whose solution and
         direction vectors fit 200 GB beside the residual ring (shorter blocks for huge sectors,
         where the ring of 2T + 1 vectors would be large)."""
+        if not args.full_solutions:
+            Gw, rep, _, rc = S.greens_proj(Hs, z, bv[None, :], tol=1e-8, max_iter=20000, window=window)
+            return Gw[:, 0].cpu().numpy(), int((rep["status"] == 0).sum()), rc, 1
         n = Hs.n
         T = 48 if 97 * 16 * n < 64e9 else 16
         per_shift = 32 * n
@@ -649,7 +658,8 @@ def bench_manybody(args, S, torch):
         "config": {"workload": f"extended Hubbard ring L={L}, t=1, U=4, V=1: ground state of {nu}+{nd} "
                                f"(n={H.n}, {form}), removal spectrum of c_(0,up) in {nu - 1}+{nd} (n={n_m}) and "
                                f"addition spectrum of c+_(0,up) in {nu + 1}+{nd} (n={Hp.n}), matrix-free, {M} "
-                               "energies, eta=0.05",
+                               "energies, eta=0.05" + (", full solutions" if args.full_solutions else
+                                                       f", projected solves with {window} stored seed candidates"),
                    "n": int(H.n), "n_target": int(n_m),
                    "n_shift": M},
         "ground_state": {"E0": E0, "E1_estimate": E1, "residual": res, "sweeps": sweeps, "cg_iterations": int(cg),
