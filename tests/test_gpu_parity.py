@@ -482,3 +482,25 @@ def test_invalid_arguments_raise():
         S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), block=3)
     with pytest.raises(ScocgError):
         S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), shifts_per_wg=65)
+
+
+@pytest.mark.parametrize("window", [0, 3])
+def test_vector_projection_on_unit_vectors_equals_greens_diag(window):
+    """greens_proj with b_j = w_j = e_j carries s_n = e_j . r_n = r_n[j] (sums of zeros and one
+    term are exact), so every pair's scalars follow the arithmetic greens_diag applies at the
+    kept row: the same G bit for bit, with and without a window of seed candidates."""
+    S = _S()
+    rng = np.random.default_rng(21)
+    L = 9
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    H = S.Hamiltonian.from_csr(Hc)
+    z = np.linspace(-6, 6, 13) + 1j * np.linspace(0.05, 0.3, 13)
+    rhs = [0, 17, 400]
+    Gd, repd, _, rcd = S.greens_diag(H, z, rhs, tol=1e-10, max_iter=6000, window=window)
+    B = torch.zeros((len(rhs), Hc.n), dtype=torch.complex128, device="cuda")
+    for c, j in enumerate(rhs):
+        B[c, j] = 1.0
+    Gp, repp, _, rcp = S.greens_proj(H, z, B, tol=1e-10, max_iter=6000, window=window)
+    assert rcp == rcd
+    assert np.array_equal(repp["iters"], repd["iters"])
+    assert np.array_equal(Gp.cpu().numpy(), Gd.cpu().numpy())
