@@ -263,8 +263,8 @@ def hubbard_fermion_op(L: int, n_up: int, n_dn: int, site: int, spin: int, creat
     tu, td = (n_up + d, n_dn) if spin == 0 else (n_up, n_dn + d)
     if not (0 <= tu <= L and 0 <= td <= L):
         raise ValueError("the target sector does not exist")
-    if x.dtype != torch.complex128 or x.numel() != comb(L, n_up) * comb(L, n_dn):
-        raise ValueError("x must be a complex128 vector of the source sector")
+    if x.dtype != torch.complex128 or not x.is_cuda or x.numel() != comb(L, n_up) * comb(L, n_dn):
+        raise ValueError("x must be a complex128 device vector of the source sector")
     x = x.contiguous()
     y = torch.empty(comb(L, tu) * comb(L, td), dtype=torch.complex128, device=x.device)
     rc = lib.hubbard_fermion_op(int(L), int(n_up), int(n_dn), int(site), int(spin), int(bool(create)), x.data_ptr(),
@@ -281,10 +281,13 @@ def greens_proj(H: Hamiltonian, z, B: torch.Tensor, W: torch.Tensor = None, allo
     _require_gpu()
     lib = C.load()
     zh, zp = _z_host(z)
-    B = B.to(torch.complex128).contiguous()
-    W = B if W is None else W.to(torch.complex128).contiguous()
-    if B.dim() != 2 or B.shape[1] != H.n or W.shape != B.shape:
-        raise ValueError("B and W must be [n_rhs, n] complex")
+    W = B if W is None else W
+    for T in (B, W):
+        if T.dtype != torch.complex128 or not T.is_cuda or T.dim() != 2 or T.shape[1] != H.n:
+            raise ValueError("B and W must be complex128 device tensors of shape [n_rhs, n]")
+    if W.shape != B.shape or W.device != B.device:
+        raise ValueError("W must match B")
+    B, W = B.contiguous(), W.contiguous()
     K, M = B.shape[0], len(zh)
     o = options(**opts)
     G = torch.empty((M, K), dtype=torch.complex128, device=B.device)
