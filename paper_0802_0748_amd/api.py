@@ -21,6 +21,19 @@ def _require_gpu():
         raise RuntimeError("the shifted-COCG library needs a HIP device; none is visible")
 
 
+def _device(device):
+    """The device for outputs: a HIP device (the library writes through device pointers)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda")
+    if dev.type != "cuda":
+        raise ValueError("outputs must live on a HIP device")
+    return dev
+
+
+def _check_dev(t: torch.Tensor, dtype, numel, name):
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor of {numel} elements")
+
+
 def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switching=True, fixed_iter=0, block=0,
             shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False, refine=0, window=0,
             schedule="auto") -> C.Opts:
@@ -181,6 +194,7 @@ def shifted_cocg_solve(H: Hamiltonian, z, B: torch.Tensor, out: torch.Tensor = N
     K, M = B.shape[0], len(zh)
     if out is None:
         out = torch.empty((K, M, H.n), dtype=torch.complex128, device=B.device)
+    _check_dev(out, torch.complex128, K * M * H.n, "out")
     o = options(**opts)
     rep = (C.PairReport * (K * M))()
     tape = ctypes.c_void_p()
@@ -198,7 +212,7 @@ def greens_diag(H: Hamiltonian, z, rhs_idx, allow_noconv=True, allow_breakdown=F
     zh, zp = _z_host(z)
     idx = np.ascontiguousarray(rhs_idx, dtype=np.int64)
     K, M = len(idx), len(zh)
-    G = torch.empty((M, K), dtype=torch.complex128, device=device or torch.device("cuda"))
+    G = torch.empty((M, K), dtype=torch.complex128, device=_device(device))
     o = options(**opts)
     rep = (C.PairReport * (K * M))()
     tape = ctypes.c_void_p()
@@ -220,7 +234,7 @@ def krylov_greens_diag(H: Hamiltonian, z, rhs_idx, nu: int, device=None):
     zh, zp = _z_host(z)
     idx = np.ascontiguousarray(rhs_idx, dtype=np.int64)
     K, M = len(idx), len(zh)
-    dev = device or torch.device("cuda")
+    dev = _device(device)
     G = torch.empty((M, K), dtype=torch.complex128, device=dev)
     ab = torch.zeros((K, 2, int(nu)), dtype=torch.float64, device=dev)
     dim = np.zeros(K, dtype=np.int32)
@@ -238,7 +252,7 @@ def ground_state(H: Hamiltonian, x0, nu: int = 200, tol: float = 1e-10, max_swee
     max_sweeps raises, unless allow_noconv (then the result is returned as it stands)."""
     _require_gpu()
     lib = C.load()
-    dev = device or torch.device("cuda")
+    dev = _device(device)
     x = torch.as_tensor(x0, dtype=torch.float64).to(dev).contiguous()
     if x.numel() != H.n:
         raise ValueError("x0 must have one entry per row")
@@ -383,10 +397,11 @@ def backward(tape: Tape, grad_G: torch.Tensor, grad_val: torch.Tensor = None) ->
     _require_gpu()
     if tape is None or tape._h is None:
         raise ValueError("no tape")
-    g = grad_G.to(torch.complex128).contiguous()
+    g = grad_G.to(device=_device(grad_G.device if grad_G.is_cuda else None), dtype=torch.complex128).contiguous()
     if tuple(g.shape) != (tape.n_shift, tape.n_rhs):
         raise ValueError("grad_G must have shape [n_shift, n_rhs]")
     if grad_val is None:
         grad_val = torch.zeros(tape.nnz, dtype=torch.float64, device=g.device)
+    _check_dev(grad_val, torch.float64, tape.nnz, "grad_val")
     C.check(C.load().backward(tape._h, g.data_ptr(), grad_val.data_ptr(), _stream_ptr()))
     return grad_val
