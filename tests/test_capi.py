@@ -85,3 +85,17 @@ def test_contour_nodes_match_oracle_quadrature():
         z2, w2 = O.contour(-13.0, 0.0, nq)
         assert np.max(np.abs(z - z2)) < 1e-12
         assert np.max(np.abs(w - w2)) < 1e-12
+
+
+def test_bindings_refuse_host_buffers():
+    """Every pointer the bindings hand to the library must be device memory: host tensors and
+    host output devices are refused before any call (no GPU needed for the checks)."""
+    import torch
+
+    from paper_0802_0748_amd import api
+
+    with pytest.raises(ValueError):
+        api._device("cpu")
+    assert api._device(None).type == "cuda"
+    with pytest.raises(ValueError):
+        api._check_dev(torch.zeros(4, dtype=torch.complex128), torch.complex128, 4, "out")
