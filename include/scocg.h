@@ -18,7 +18,8 @@
  *    complex128 / hipDoubleComplex.
  *  - "device" pointers are HIP device memory owned by the caller; the library
  *    never frees them and they must stay valid until the call returns.  "host"
- *    pointers are ordinary CPU memory.
+ *    pointers are ordinary CPU memory.  A device argument that is plain host memory
+ *    (not device, pinned or managed) is refused with SCOCG_EINVAL before any work.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Solver calls enqueue work on that stream and return after it has finished
  *    (the iteration is steered from the host between blocks of iterations).

@@ -27,6 +27,24 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+// Buffers the kernels read or write must be device-accessible (device, pinned host or managed
+// memory): a plain host pointer would make the GPU fault, so it is refused up front.
+static bool device_ok(const void *p)
+{
+    if (!p) return true;  // optional buffers are checked for null by the caller
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type != hipMemoryTypeUnregistered && a.devicePointer != nullptr;
+}
+#define REQUIRE_DEVICE(...)                                                                                    \
+    do {                                                                                                       \
+        for (const void *p_ : {__VA_ARGS__})                                                                   \
+            if (!device_ok(p_)) return fail(SCOCG_EINVAL, "a vector or output argument is not device memory"); \
+    } while (0)
+
 #define HIPCHK(expr)                                                                         \
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \
@@ -998,6 +1016,7 @@ extern "C" int shifted_cocg_solve(scocg_csr_t H, int64_t n_shift, const double *
 {
     g_err.clear();
     if (!H || !z || !B || !o) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)B, (const void *)X);
     const bool want_tape = tape && o->keep_tape;
     if (!X && !want_tape) return fail(SCOCG_EINVAL, "X is null and no tape was requested");
     SolveRequest rq{};
@@ -1038,6 +1057,7 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
 {
     g_err.clear();
     if (!H || !z || !rhs_idx || !G) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)G, (const void *)ab);
     const int64_t n = H->d.n;
     if (n_shift < 1 || n_rhs < 1) return fail(SCOCG_EINVAL, "n_shift and n_rhs must be positive");
     // finite-precision recurrences run past n (the basis loses orthogonality); the limit keeps
@@ -1125,6 +1145,7 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
 {
     g_err.clear();
     if (!H || !x0 || !psi || !E) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)x0, (const void *)psi);
     if (nu < 2 || nu > (1 << 20)) return fail(SCOCG_EINVAL, "nu must be in [2, 2^20]");
     if (!(tol > 0) || max_sweeps < 0) return fail(SCOCG_EINVAL, "tol must be positive and max_sweeps >= 0");
     hipStream_t st = (hipStream_t)stream;
@@ -1277,6 +1298,7 @@ extern "C" int hubbard_fermion_op(int32_t L, int32_t n_up, int32_t n_dn, int32_t
 {
     g_err.clear();
     if (!x || !y) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)x, (const void *)y);
     if (L < 3 || L > 30) return fail(SCOCG_EINVAL, "L must be in [3, 30]");
     if (n_up < 0 || n_up > L || n_dn < 0 || n_dn > L) return fail(SCOCG_EINVAL, "electron counts out of range");
     if (site < 0 || site >= L || (spin != 0 && spin != 1)) return fail(SCOCG_EINVAL, "site or spin out of range");
@@ -1314,6 +1336,7 @@ extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int6
 {
     g_err.clear();
     if (!H || !z || !rhs_idx || !o || !G) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)G);
     for (int64_t j = 0; j < n_rhs; ++j)
         if (rhs_idx[j] < 0 || rhs_idx[j] >= H->d.n) return fail(SCOCG_EINVAL, "rhs_idx out of range");
     const bool want_tape = tape && o->keep_tape;
@@ -1356,6 +1379,7 @@ extern "C" int greens_proj(scocg_csr_t H, int64_t n_shift, const double *z, int6
 {
     g_err.clear();
     if (!H || !z || !B || !W || !o || !G) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)B, (const void *)W, (const void *)G);
     SolveRequest rq{};
     rq.H = H;
     rq.M = n_shift;
@@ -1378,6 +1402,7 @@ extern "C" int greens_diag_batched(int64_t n_problems, const scocg_csr_t *H, con
 {
     g_err.clear();
     if (n_problems <= 0 || !H || !n_rhs || !rhs_idx || !z || !o || !G) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)G);
     SolveRequest rq{};
     std::vector<int64_t> idx;
     for (int64_t q = 0; q < n_problems; ++q) {
@@ -1412,6 +1437,7 @@ extern "C" int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double
 {
     g_err.clear();
     if (!H || !z || !w || !rhs_idx || !o || !E_band) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)rho_nnz, (const void *)E_band, (const void *)dE_dval);
     if (n_quad <= 0 || n_rhs <= 0) return fail(SCOCG_EINVAL, "n_quad and n_rhs must be positive");
     if (matrix_free(H)) return fail(SCOCG_EINVAL, "density_matrix_energy needs a stored matrix");
     const DevCSR &d = H->d;
@@ -1465,6 +1491,7 @@ extern "C" int backward(scocg_tape_t tape, const double *grad_G, double *grad_va
 {
     g_err.clear();
     if (!tape || !grad_G || !grad_val) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)grad_G, (const void *)grad_val);
     if (matrix_free(tape->H)) return fail(SCOCG_EINVAL, "backward needs a stored matrix");
     const DevCSR &d = tape->H->d;
     int64_t maxrow = 0;

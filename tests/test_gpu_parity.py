@@ -504,3 +504,34 @@ def test_vector_projection_on_unit_vectors_equals_greens_diag(window):
     assert rcp == rcd
     assert np.array_equal(repp["iters"], repd["iters"])
     assert np.array_equal(Gp.cpu().numpy(), Gd.cpu().numpy())
+
+
+def test_c_abi_refuses_host_buffers():
+    """Vector and output arguments must be device memory: plain host buffers passed through the
+    C ABI are refused with EINVAL before any kernel runs (pinned and device memory pass)."""
+    import ctypes
+
+    from paper_0802_0748_amd import _capi as C
+
+    S = _S()
+    lib = C.load()
+    Hc, z, B = _problem(50, 4)
+    H = S.Hamiltonian.from_csr(Hc)
+    zh = np.ascontiguousarray(z.astype(np.complex128)).view(np.float64)
+    o = S.options(tol=1e-8)
+    Bh = np.ascontiguousarray(B[:1])  # host memory
+    Xd = torch.empty((1, len(z), Hc.n), dtype=torch.complex128, device="cuda")
+    rc = lib.shifted_cocg_solve(H.handle, len(z), zh.ctypes.data, 1, Bh.ctypes.data, ctypes.byref(o), Xd.data_ptr(),
+                                None, None, None)
+    assert rc == C.EINVAL and "device memory" in lib.scocg_last_error().decode()
+    Bd = torch.from_numpy(Bh).cuda()
+    Xh = np.zeros((1, len(z), Hc.n), dtype=np.complex128)
+    rc = lib.shifted_cocg_solve(H.handle, len(z), zh.ctypes.data, 1, Bd.data_ptr(), ctypes.byref(o), Xh.ctypes.data,
+                                None, None, None)
+    assert rc == C.EINVAL
+    xh = np.zeros(400, dtype=np.complex128)
+    yh = np.zeros(400, dtype=np.complex128)
+    assert lib.hubbard_fermion_op(6, 3, 3, 0, 0, 0, xh.ctypes.data, yh.ctypes.data, None) == C.EINVAL
+    # device buffers still pass
+    X, _, _, rc = S.shifted_cocg_solve(H, z, Bd, fixed_iter=5)
+    assert rc == 0
