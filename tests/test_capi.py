@@ -99,3 +99,21 @@ def test_bindings_refuse_host_buffers():
     assert api._device(None).type == "cuda"
     with pytest.raises(ValueError):
         api._check_dev(torch.zeros(4, dtype=torch.complex128), torch.complex128, 4, "out")
+
+
+def test_null_arguments_are_refused_without_a_device():
+    """Null handles or buffers are EINVAL with a message, decided before any device work
+    (so this runs on the CPU)."""
+    import ctypes
+
+    from paper_0802_0748_amd import _capi as C
+
+    lib = C.load()
+    o = C.Opts()
+    lib.scocg_default_opts(ctypes.byref(o))
+    z = np.array([0.0, 0.1])
+    assert lib.greens_proj(None, 1, z.ctypes.data, 1, None, None, ctypes.byref(o), None, None, None) == C.EINVAL
+    assert "null" in lib.scocg_last_error().decode()
+    assert lib.shifted_cocg_solve(None, 1, z.ctypes.data, 1, None, ctypes.byref(o), None, None, None, None) == C.EINVAL
+    assert lib.krylov_greens_diag(None, 1, z.ctypes.data, 1, None, 4, None, None, None, None) == C.EINVAL
+    assert lib.hubbard_fermion_op(6, 3, 3, 0, 0, 0, None, None, None) == C.EINVAL
