@@ -603,6 +603,7 @@ def bench_manybody(args, S, torch):
         where the ring of 2T + 1 vectors would be large)."""
         if not args.full_solutions:
             Gw, rep, _, rc = S.greens_proj(Hs, z, bv[None, :], tol=1e-8, max_iter=20000, window=window)
+            spectrum.iters = int(rep["iters"].max())
             return Gw[:, 0].cpu().numpy(), int((rep["status"] == 0).sum()), rc, 1
         n = Hs.n
         T = 48 if 97 * 16 * n < 64e9 else 16
@@ -611,6 +612,7 @@ def bench_manybody(args, S, torch):
         G, conv, rc_all = [], 0, 0
         for k0 in range(0, len(z), Mw):
             X, rep, _, rc = S.shifted_cocg_solve(Hs, z[k0:k0 + Mw], bv[None, :], tol=1e-8, max_iter=20000, block=T)
+            spectrum.iters = max(getattr(spectrum, "iters", 0), int(rep["iters"].max()))
             G.append((X[0] @ bv).cpu().numpy())
             conv += int((rep["status"] == 0).sum())
             rc_all = max(rc_all, rc)
@@ -626,8 +628,17 @@ def bench_manybody(args, S, torch):
     G, conv, rc, nw = spectrum(Hm, b, z)
     torch.cuda.synchronize()
     t_sp = time.perf_counter() - t0
+    # the same removal spectrum by Krylov-subspace diagonalization from b (Sec. 3.2): as many
+    # steps of the recurrence as the shifted solve took iterations, then a continued fraction
+    t0 = time.perf_counter()
+    Gk, _, mk = S.krylov_greens_vec(Hm, z, b, spectrum.iters)
+    torch.cuda.synchronize()
+    t_kr = time.perf_counter() - t0
+    dev_kr = float(np.max(np.abs(Gk.cpu().numpy() - G)) / np.max(np.abs(G)))
+    print(f"[bench] removal spectrum by the continued fraction: {mk} steps, {t_kr:.2f} s, largest deviation "
+          f"from shifted COCG {dev_kr:.1e} (relative to max |G|)", file=sys.stderr, flush=True)
     n_m = Hm.n
-    del Hm
+    del Hm, Gk
     A = -G.imag / np.pi
     occ = float((b.conj() @ b).real)  # total spectral weight <psi0|n_{0,up}|psi0>
     print(f"[bench] ionization spectrum: {M} energies ({nw} solve(s)), rc={rc}, {conv}/{M} converged, {t_sp:.2f} s; "
@@ -666,6 +677,7 @@ def bench_manybody(args, S, torch):
                          "seconds": t_gs},
         "spectrum": {"seconds": t_sp, "converged": conv, "total_weight": occ, "occupation": nu / L,
                      "peak_w": float(w[np.argmax(A)])},
+        "removal_by_continued_fraction": {"steps": mk, "seconds": t_kr, "max_rel_deviation_from_cocg": dev_kr},
         "addition_spectrum": {"seconds": t_ad, "converged": conv_p, "total_weight": occ_p,
                               "removal_plus_addition": occ + occ_p, "peak_w": float(w[np.argmax(Ap)])},
     }

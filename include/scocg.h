@@ -188,6 +188,22 @@ int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t 
                        int32_t nu, double *G, double *ab, int32_t *dim, void *stream);
 
 /*
+ * <b|(z_k - H)^{-1}|b> for one real start vector b by Krylov-subspace diagonalization
+ * (Sec. 3.2, eq. Ham_in_KS): nu steps of the three-term recurrence from b/|b| (ending early at
+ * an invariant subspace), then |b|^2 times [(z_k - T)^{-1}]_11 of the reduced Hamiltonian T as a
+ * continued fraction; the spectral function of b (for b = c|psi0>, a many-electron excitation
+ * spectrum, Sec. 4.2) without one linear solve per shift.
+ *   b     device, [n] real, nonzero
+ *   G     device, [n_shift] complex output
+ *   ab    device, [2][nu] (the a and b coefficients as in krylov_greens_diag), or NULL
+ *   dim   host, the subspace dimension reached, or NULL
+ * H is a stored matrix or a matrix-free Hubbard operator.  Errors: EINVAL (null or bad
+ * arguments, a zero start vector, nu outside [1, 2^20]), ENOMEM, EHIP.  Synchronous.
+ */
+int krylov_greens_vec(scocg_csr_t H, int64_t n_shift, const double *z, const double *b, int32_t nu, double *G,
+                      double *ab, int32_t *dim, void *stream);
+
+/*
  * Ground state of a many-electron Hamiltonian (Sec. 2.2: the Lanczos method for an estimate,
  * then the CG method as inverse iteration, repeated until the residual norm is small).
  * nu steps of the three-term recurrence from x0 give the reduced Hamiltonian, whose lowest

@@ -71,6 +71,7 @@ EXPORTED = [
     "greens_diag_batched",
     "greens_proj",
     "krylov_greens_diag",
+    "krylov_greens_vec",
     "ground_state",
     "hubbard_fermion_op",
     "density_matrix_energy",
@@ -107,6 +108,8 @@ def load():
     lib.hubbard_upload.restype = i32
     lib.krylov_greens_diag.argtypes = [P, i64, P, i64, P, i32, P, P, P, P]
     lib.krylov_greens_diag.restype = i32
+    lib.krylov_greens_vec.argtypes = [P, i64, P, P, i32, P, P, P, P]
+    lib.krylov_greens_vec.restype = i32
     lib.ground_state.argtypes = [P, P, i32, ctypes.c_double, i32, P, P, P, P, P]
     lib.ground_state.restype = i32
     lib.hubbard_fermion_op.argtypes = [i32, i32, i32, i32, i32, i32, P, P, P]

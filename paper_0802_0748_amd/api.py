@@ -244,6 +244,32 @@ def krylov_greens_diag(H: Hamiltonian, z, rhs_idx, nu: int, device=None):
     return G, ab, dim
 
 
+def krylov_greens_vec(H: Hamiltonian, z, b, nu: int, device=None):
+    """<b|(z_k - H)^{-1}|b> for a real start vector b by Krylov-subspace diagonalization (nu
+    steps of the three-term recurrence from b / |b|, then the continued fraction).  Returns
+    (G [n_shift] complex128, ab [2, nu] float64, subspace dimension)."""
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    dev = _device(device)
+    bt = torch.as_tensor(b)
+    if bt.is_complex():
+        if bool(torch.any(bt.imag != 0)):
+            raise ValueError("the start vector must be real")
+        bt = bt.real
+    bt = bt.to(device=dev, dtype=torch.float64).contiguous()
+    if bt.numel() != H.n:
+        raise ValueError("b must have one entry per row")
+    M = len(zh)
+    G = torch.empty(M, dtype=torch.complex128, device=dev)
+    ab = torch.zeros((2, int(nu)), dtype=torch.float64, device=dev)
+    dim = ctypes.c_int32()
+    rc = lib.krylov_greens_vec(H.handle, M, zp, bt.data_ptr(), int(nu), G.data_ptr(), ab.data_ptr(),
+                               ctypes.byref(dim), _stream_ptr())
+    C.check(rc)
+    return G, ab, dim.value
+
+
 def ground_state(H: Hamiltonian, x0, nu: int = 200, tol: float = 1e-10, max_sweeps: int = 50, device=None,
                  allow_noconv=False):
     """Lowest eigenpair of H: an estimate from nu steps of the three-term recurrence started at

@@ -1103,6 +1103,7 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
     s.n = n;
     s.K = Kp;
     s.rb = LZ_RB;
+    s.gscale = 1.0;
     s.nblk = nblk;
     s.nu = nu;
     s.V[0] = bV0.as<double>();
@@ -1140,6 +1141,97 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
 // (bisection on the reduced Hamiltonian) and, run a second time, accumulates the Ritz vector;
 // inverse iteration then refines it: each sweep solves (sigma - H) y = psi with one shift
 // sigma below the spectrum (where COCG is CG) and normalizes y, until ||H psi - E psi|| <= tol.
+// <b|(z_k - H)^{-1}|b> for a real start vector b by the Krylov-subspace method (Sec. 3.2):
+// the three-term recurrence from b/|b|, then |b|^2 times the continued fraction of the reduced
+// Hamiltonian.
+extern "C" int krylov_greens_vec(scocg_csr_t H, int64_t n_shift, const double *z, const double *b, int32_t nu,
+                                 double *G, double *ab, int32_t *dim, void *stream)
+{
+    g_err.clear();
+    if (!H || !z || !b || !G) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)b, (const void *)G, (const void *)ab);
+    if (n_shift < 1) return fail(SCOCG_EINVAL, "n_shift must be positive");
+    if (nu < 1 || nu > (1 << 20)) return fail(SCOCG_EINVAL, "nu must be in [1, 2^20]");
+    for (int64_t k = 0; k < 2 * n_shift; ++k)
+        if (!std::isfinite(z[k])) return fail(SCOCG_EINVAL, "non-finite shift");
+    hipStream_t st = (hipStream_t)stream;
+    g_timing = scocg_timing{};
+    const int64_t n = H->d.n;
+    const int64_t nblk = (n + LZ_TILE - 1) / LZ_TILE;
+    DevBuf bxs, bV0, bV1, bW0, bW1, bpart, bab, bst, bz, bscal;
+    hipError_t e = hipSuccess;
+    auto A = [&](DevBuf &buf, size_t bytes) {
+        if (e == hipSuccess) e = buf.alloc(bytes);
+    };
+    A(bxs, n * sizeof(double));
+    for (DevBuf *v : {&bV0, &bV1, &bW0, &bW1}) A(*v, (size_t)n * sizeof(double));
+    A(bpart, (size_t)2 * nblk * sizeof(double));
+    if (!ab) A(bab, (size_t)2 * nu * sizeof(double));
+    A(bst, sizeof(LzRhs));
+    A(bz, (size_t)n_shift * sizeof(double2));
+    A(bscal, 8 * sizeof(double));
+    if (e != hipSuccess) return fail(SCOCG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    SvDev v{};
+    v.hub = H->d.d_hub;
+    v.slice_ptr = H->d.d_slice_ptr;
+    v.slice_w = H->d.d_slice_w;
+    v.ell_col = H->d.d_ell_col;
+    v.ell_val = H->d.d_ell_val;
+    v.n = n;
+    v.nblk = nblk;
+    v.part = bpart.as<double>();
+    v.scal = bscal.as<double>();
+    double *xs = bxs.as<double>();
+    HIPCHK(hipMemcpyAsync(xs, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(sv_normalize(v, xs, nullptr, st));
+    double nb2 = 0;
+    HIPCHK(hipMemcpyAsync(&nb2, bscal.as<double>() + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!(nb2 > 0) || !std::isfinite(nb2)) return fail(SCOCG_EINVAL, "the start vector must be nonzero and finite");
+    LzRhs h0{};
+    h0.j = -1;
+    HIPCHK(hipMemcpyAsync(bst.ptr, &h0, sizeof(LzRhs), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bz.ptr, z, n_shift * sizeof(double2), hipMemcpyHostToDevice, st));
+    LzDev s{};
+    s.hub = v.hub;
+    s.slice_ptr = v.slice_ptr;
+    s.slice_w = v.slice_w;
+    s.ell_col = v.ell_col;
+    s.ell_val = v.ell_val;
+    s.n = n;
+    s.K = 1;
+    s.rb = 1;
+    s.nblk = nblk;
+    s.nu = nu;
+    s.V[0] = bV0.as<double>();
+    s.V[1] = bV1.as<double>();
+    s.W[0] = bW0.as<double>();
+    s.W[1] = bW1.as<double>();
+    s.part = bpart.as<double>();
+    s.ab = ab ? ab : bab.as<double>();
+    s.st = bst.as<LzRhs>();
+    s.x0 = xs;
+    s.gscale = nb2;
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, st));
+    for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
+    HIPCHK(launch_lanczos_greens(s, bz.as<double2>(), n_shift, 1, (double2 *)G, st));
+    HIPCHK(hipEventRecord(t1, st));
+    LzRhs hf{};
+    HIPCHK(hipMemcpyAsync(&hf, bst.ptr, sizeof(LzRhs), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (dim) *dim = hf.m;
+    g_timing.total_ms = ms;
+    g_timing.iterations = hf.m;
+    return SCOCG_OK;
+}
+
 extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double tol, int32_t max_sweeps,
                             double *psi, double *E, double *res, int32_t *sweeps, void *stream)
 {

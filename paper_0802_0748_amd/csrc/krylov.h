@@ -46,6 +46,7 @@ struct LzDev {
     const double *x0;    // start vectors [K][n], unit norm, or null for the unit vectors e_j
     double *acc;         // null, or [K][n]: accumulates sum_n coef[k][n] K_n (Ritz vectors)
     const double *coef;  // [K][nu] with acc
+    double gscale;       // G is scaled by this: 1 for unit start vectors, |b|^2 for a start vector b
 };
 
 // Single real vector of n rows on the stored matrix or the matrix-free operator; one partial

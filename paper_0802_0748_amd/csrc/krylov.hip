@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(WG) k_lz_greens(LzDev s, const double2 *__rest
         const double bb = b[t] * b[t];
         g = cdiv(cmk(1, 0), cmk(zk.x - a[t] - bb * g.x, zk.y - bb * g.y));
     }
-    G[k * K + r] = g;
+    G[k * K + r] = make_double2(s.gscale * g.x, s.gscale * g.y);
 }
 
 // Lowest two eigenvalues of the reduced Hamiltonian by bisection on Sturm counts (the number
