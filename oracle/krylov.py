@@ -34,9 +34,15 @@ def lanczos(H, j: int, nu: int):
     """Coefficients of the Krylov basis of |j>: a[0..m), b[0..m) with b[n] = b_{n+2} in the
     1-based notation above (b[n] couples K_{n+1} and K_{n+2}; b[m-1] is the leftover norm),
     m <= nu the subspace dimension reached."""
-    v_prev = np.zeros(H.n)
     v = np.zeros(H.n)
     v[j] = 1.0
+    return lanczos_from(H, v, nu)
+
+
+def lanczos_from(H, v, nu: int):
+    """The same recurrence from a real unit start vector |K_1> = v."""
+    v_prev = np.zeros(H.n)
+    v = np.asarray(v, dtype=float).copy()
     b_n = 0.0
     a, b = [], []
     for n in range(nu):
@@ -75,3 +81,13 @@ def krylov_greens_diag(H, z, rhs_idx, nu: int):
         a, b = lanczos(H, int(j), nu)
         cols.append(greens_from_subspace(a, b, z))
     return np.stack(cols, axis=1)
+
+
+def krylov_greens_vec(H, z, b, nu: int):
+    """<b|(z - H)^{-1}|b> in the nu-dimensional Krylov subspace of a real start vector b:
+    |b|^2 times the subspace Green's function of b / |b| (the method of Sec. 3.2 with the
+    start vector b instead of a unit vector)."""
+    b = np.asarray(b, dtype=float)
+    nb2 = float(b @ b)
+    a, c = lanczos_from(H, b / np.sqrt(nb2), nu)
+    return nb2 * greens_from_subspace(a, c, z)

@@ -80,3 +80,26 @@ def test_invariant_subspace_stops_the_recurrence():
     z = np.array([-1.0 + 0.05j, 0.2 + 0.3j, 2.0 + 0.01j])
     exact = np.array([np.linalg.inv(zk * np.eye(20) - H.to_dense())[0, 0] for zk in z])
     assert np.max(np.abs(K.greens_from_subspace(a, b, z) - exact) / np.abs(exact)) < 1e-12
+
+
+def test_start_vector_subspace_reaches_the_exact_projected_resolvent():
+    """From a real start vector b: at full dimension |b|^2 [(z - T)^{-1}]_11 is b^T (z - H)^{-1} b
+    (the dense definition), and the moments b^T H^k b equal |b|^2 (T^k)_11 for k < 2m."""
+    rng = np.random.default_rng(12)
+    n = 18
+    H = random_sparse_symmetric(n, 0.4, rng, diag_scale=2.0)
+    D = H.to_dense()
+    b = rng.normal(size=n)
+    z = np.linspace(-4, 4, 9) + 0.3j
+    G = K.krylov_greens_vec(H, z, b, n)
+    exact = np.array([b @ np.linalg.solve(zk * np.eye(n) - D, b.astype(complex)) for zk in z])
+    assert np.max(np.abs(G - exact) / np.abs(exact)) < 1e-9
+    m = 5
+    a, c = K.lanczos_from(H, b / np.linalg.norm(b), m)
+    T = K.reduced_hamiltonian(a, c)
+    nb2 = b @ b
+    hv, tk = b.copy(), np.eye(len(a))[0]
+    for k in range(2 * m):
+        assert abs(b @ hv - nb2 * tk[0]) < 1e-9 * max(1.0, abs(b @ hv))
+        hv = D @ hv
+        tk = T @ tk
