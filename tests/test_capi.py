@@ -117,3 +117,26 @@ def test_null_arguments_are_refused_without_a_device():
     assert lib.shifted_cocg_solve(None, 1, z.ctypes.data, 1, None, ctypes.byref(o), None, None, None, None) == C.EINVAL
     assert lib.krylov_greens_diag(None, 1, z.ctypes.data, 1, None, 4, None, None, None, None) == C.EINVAL
     assert lib.hubbard_fermion_op(6, 3, 3, 0, 0, 0, None, None, None) == C.EINVAL
+
+
+def test_product_path_fails_loudly(monkeypatch, tmp_path):
+    """There is no CPU fallback: without a HIP device every entry of the binding raises, and a
+    missing library is an ImportError, never a silent substitute."""
+    import torch
+
+    from paper_0802_0748_amd import _capi as C
+    from paper_0802_0748_amd import api
+    from workloads import random_sparse_symmetric
+
+    if not torch.cuda.is_available():
+        H = random_sparse_symmetric(12, 0.3, np.random.default_rng(0))
+        with pytest.raises(RuntimeError, match="HIP device"):
+            api.Hamiltonian.from_csr(H)
+        with pytest.raises(RuntimeError, match="HIP device"):
+            api.Hamiltonian.hubbard(6, 3, 3)
+        with pytest.raises(RuntimeError, match="HIP device"):
+            api.greens_diag(None, [0.1j], [0])
+    monkeypatch.setattr(C, "_lib", None)
+    monkeypatch.setattr(C, "LIB_PATH", str(tmp_path / "libscocg.so"))
+    with pytest.raises(ImportError, match="not built"):
+        C.load()
