@@ -76,6 +76,24 @@ struct DevBuf {
     T *as() const { return (T *)ptr; }
 };
 
+// A pair of timing events destroyed when the owner goes out of scope (also on error returns).
+struct TimerEvents {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    TimerEvents() = default;
+    TimerEvents(const TimerEvents &) = delete;
+    TimerEvents &operator=(const TimerEvents &) = delete;
+    ~TimerEvents()
+    {
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+    }
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreate(&t0);
+        return e == hipSuccess ? hipEventCreate(&t1) : e;
+    }
+};
+
 struct GraphPair {
     hipStream_t cap = nullptr;
     hipGraph_t ga[2] = {nullptr, nullptr}, gb = nullptr;
@@ -562,17 +580,9 @@ int solve(SolveRequest &rq, hipStream_t st)
     const size_t esz = o.precision == 0 ? sizeof(double2) : sizeof(float2);
 
     g_timing = scocg_timing{};
-    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
-    HIPCHK(hipEventCreate(&ev_t0));
-    HIPCHK(hipEventCreate(&ev_t1));
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard()
-        {
-            if (a) (void)hipEventDestroy(a);
-            if (b) (void)hipEventDestroy(b);
-        }
-    } evg{ev_t0, ev_t1};
+    TimerEvents tev;
+    HIPCHK(tev.create());
+    hipEvent_t ev_t0 = tev.t0, ev_t1 = tev.t1;
     HIPCHK(hipEventRecord(ev_t0, st));
 
     SolveDev s{};
@@ -1113,9 +1123,9 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
     s.part = bpart.as<double>();
     s.ab = ab ? ab : bab.as<double>();
     s.st = bst.as<LzRhs>();
-    hipEvent_t t0, t1;
-    HIPCHK(hipEventCreate(&t0));
-    HIPCHK(hipEventCreate(&t1));
+    TimerEvents evs;
+    HIPCHK(evs.create());
+    hipEvent_t t0 = evs.t0, t1 = evs.t1;
     HIPCHK(hipEventRecord(t0, st));
     for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
     HIPCHK(launch_lanczos_greens(s, bz.as<double2>(), n_shift, n_rhs, (double2 *)G, st));
@@ -1124,8 +1134,6 @@ extern "C" int krylov_greens_diag(scocg_csr_t H, int64_t n_shift, const double *
     HIPCHK(hipStreamSynchronize(st));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     int64_t steps = 0;
     for (int64_t c = 0; c < n_rhs; ++c) {
         steps += hst[c].m;
@@ -1212,9 +1220,9 @@ extern "C" int krylov_greens_vec(scocg_csr_t H, int64_t n_shift, const double *z
     s.st = bst.as<LzRhs>();
     s.x0 = xs;
     s.gscale = nb2;
-    hipEvent_t t0, t1;
-    HIPCHK(hipEventCreate(&t0));
-    HIPCHK(hipEventCreate(&t1));
+    TimerEvents evs;
+    HIPCHK(evs.create());
+    hipEvent_t t0 = evs.t0, t1 = evs.t1;
     HIPCHK(hipEventRecord(t0, st));
     for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
     HIPCHK(launch_lanczos_greens(s, bz.as<double2>(), n_shift, 1, (double2 *)G, st));
@@ -1224,8 +1232,6 @@ extern "C" int krylov_greens_vec(scocg_csr_t H, int64_t n_shift, const double *z
     HIPCHK(hipStreamSynchronize(st));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     if (dim) *dim = hf.m;
     g_timing.total_ms = ms;
     g_timing.iterations = hf.m;
@@ -1298,9 +1304,9 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     s.ab = bab.as<double>();
     s.st = bst.as<LzRhs>();
     s.x0 = xs;
-    hipEvent_t t0, t1;
-    HIPCHK(hipEventCreate(&t0));
-    HIPCHK(hipEventCreate(&t1));
+    TimerEvents evs;
+    HIPCHK(evs.create());
+    hipEvent_t t0 = evs.t0, t1 = evs.t1;
     HIPCHK(hipEventRecord(t0, st));
     HIPCHK(hipMemcpyAsync(bst.ptr, hst.data(), sizeof(LzRhs), hipMemcpyHostToDevice, st));
     for (int it = 0; it < nu; ++it) HIPCHK(launch_lanczos_step(s, it, st));
@@ -1370,8 +1376,6 @@ extern "C" int ground_state(scocg_csr_t H, const double *x0, int32_t nu, double 
     HIPCHK(hipStreamSynchronize(st));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     E[0] = Ecur;
     E[1] = eig[1];
     if (res) *res = rcur;
