@@ -179,6 +179,27 @@ def test_matrix_free_operator_gives_the_stored_coefficients(L, nu, nd):
     assert np.max(np.abs(Gm.cpu().numpy()[:, 2] - ref) / np.abs(ref)) < 1e-10
 
 
+@pytest.mark.parametrize("n,nu", [(1111, 30), (300, 12), (64, 1)])
+def test_start_vector_coefficients_match_reference(n, nu):
+    """krylov_greens_vec from a random real b against the reference recurrence from b / |b|:
+    coefficients and |b|^2-scaled G within 1e-10 (several tiles and a ragged tail)."""
+    S = _S()
+    rng = np.random.default_rng(n + 5)
+    Hc = _scaled(random_sparse_symmetric(n, 8.0 / n, rng, diag_scale=1.0))
+    H = S.Hamiltonian.from_csr(Hc)
+    b = rng.normal(size=n) * 3.0
+    z = np.linspace(-1.2, 1.2, 9) + 0.05j
+    G, ab, dim = S.krylov_greens_vec(H, z, b, nu)
+    G, ab = G.cpu().numpy(), ab.cpu().numpy()
+    a, c = K.lanczos_from(Hc, b / np.linalg.norm(b), nu)
+    m = len(a)
+    assert dim == m
+    assert np.max(np.abs(ab[0, :m] - a)) < 1e-10
+    assert np.max(np.abs(ab[1, :m] - c)) < 1e-10
+    ref = K.krylov_greens_vec(Hc, z, b, nu)
+    assert np.max(np.abs(G - ref) / np.abs(ref)) < 1e-10
+
+
 def test_start_vector_continued_fraction():
     """krylov_greens_vec: with as many steps as rows the subspace is the whole space and
     |b|^2 [(z - T)^{-1}]_11 is b^T (z - H)^{-1} b (20 rows, as for the unit start vectors above:
