@@ -817,8 +817,8 @@ def main():
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the solver runs on a single device).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the solver runs on a "
+              "single device and has no multi-GPU sharding.", file=sys.stderr)
         return 2
     import torch
 

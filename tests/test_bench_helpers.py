@@ -48,3 +48,11 @@ def test_hot_path_bytes():
     assert h["bytes"] == 1e9 + 10 * 8 * 16 * 1000 + 12e3 * 10
     assert h["achieved"] == pytest.approx(h["bytes"] / 1e9 / 2.0)
     assert h["bound"] == "hbm" and h["peak"] == bench.HBM_PEAK_GBS
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    import subprocess
+
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
