@@ -6,7 +6,9 @@
 * the hopping part of the sector matrix of workloads.hubbard (an independent construction)
   equals -t sum_i (c+_{i+1} c_i + c+_i c_{i+1}) composed from the operators;
 * the free ring (U = V = 0) has the closed-form ground energy of filled periodic
-  single-particle levels (which the Jordan-Wigner sign of the closing bond ensures).
+  single-particle levels (which the Jordan-Wigner sign of the closing bond ensures);
+* the projected resolvent equals its Lehmann sum over eigenpairs and its large-|z| expansion,
+  and the removal weight of c_{0,up}|psi0> is the filling N_up / L.
 """
 
 import numpy as np
@@ -117,3 +119,27 @@ def test_sector_dimension_of_the_papers_many_electron_problem():
     assert len(up) ** 2 == g["dimension"]
     assert np.all(np.diff(up) > 0)  # increasing patterns, each with 6 bits set
     assert all(bin(int(s)).count("1") == g["electrons_per_spin"] for s in up[:: max(1, len(up) // 97)])
+
+
+def test_projected_resolvent_spectral_form_and_removal_sum_rule():
+    """<b|(z - H)^{-1}|b> equals the Lehmann sum over eigenpairs (v_a . b)^2 / (z - e_a); it
+    decays as |b|^2 / z + b^T H b / z^2 at large |z|; and for b = c_{0,up}|psi0> of the
+    translation-invariant ring the total removal weight |b|^2 is the up-spin filling N_up / L."""
+    L, nu, nd = 6, 3, 3
+    D = hubbard_ring(L, nu, nd, t=1.0, U=4.0, V=1.0).to_dense()
+    E0, psi, E1 = MB.ground_state(D)
+    assert E1 - E0 > 1e-6  # nondegenerate, so psi0 is translation invariant
+    b, sec = MB.fermion_op(L, nu, nd, 0, 0, False, psi)
+    assert sec == (nu - 1, nd)
+    assert abs(b @ b - nu / L) < 1e-12
+    Dm = hubbard_ring(L, *sec, t=1.0, U=4.0, V=1.0).to_dense()
+    z = E0 - np.linspace(-6, 6, 13) + 0.2j
+    G = MB.projected_resolvent(Dm, b, z)
+    e, v = np.linalg.eigh(Dm)
+    w = (v.T @ b) ** 2
+    lehmann = np.array([np.sum(w / (zk - e)) for zk in z])
+    assert np.max(np.abs(G - lehmann)) < 1e-11 * np.max(np.abs(G))
+    zb = np.array([1e4 + 3e3j, -2e4 + 1e3j])
+    Gb = MB.projected_resolvent(Dm, b, zb)
+    asym = (b @ b) / zb + (b @ Dm @ b) / zb**2
+    assert np.max(np.abs(Gb - asym) / np.abs(asym)) < 1e-6
