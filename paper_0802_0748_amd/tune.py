@@ -10,6 +10,7 @@ by the problem signature (n, stored entries, right-hand sides, shifts, precision
 
 import json
 import os
+import tempfile
 import time
 
 import torch
@@ -66,11 +67,24 @@ def tune(H: "api.Hamiltonian", z, B: torch.Tensor, precision="fp64", iters=64, c
     del out
     best["candidates"] = [list(r) for r in results]
     if cache:
-        os.makedirs(os.path.dirname(cache), exist_ok=True)
-        table = _load(cache)
-        table[key] = best
-        tmp = cache + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(table, f, indent=1)
-        os.replace(tmp, cache)
+        _store(cache, key, best)
     return best
+
+
+def _store(path, key, entry):
+    """Add one entry to the cache file.  Each writer fills a temporary file of its own and
+    renames it over the cache, so concurrent tuners never leave a torn file (the last rename
+    wins; a lost entry is only re-tuned)."""
+    d = os.path.dirname(path) or "."
+    os.makedirs(d, exist_ok=True)
+    table = _load(path)
+    table[key] = entry
+    fd, tmp = tempfile.mkstemp(prefix=".tune-", suffix=".json", dir=d)
+    try:
+        with os.fdopen(fd, "w") as f:
+            json.dump(table, f, indent=1)
+        os.replace(tmp, path)
+    except BaseException:
+        if os.path.exists(tmp):
+            os.remove(tmp)
+        raise
