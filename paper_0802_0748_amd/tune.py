@@ -5,7 +5,8 @@ the block length T (iterations whose updates are applied in one pass) and the nu
 of shifts one workgroup walks through.  The tuner times short fixed-iteration solves
 of the caller's problem for each candidate on the device (HIP events inside the
 library) and keeps the fastest per iteration.  Results are cached in a JSON file keyed
-by the problem signature (n, stored entries, right-hand sides, shifts, precision).
+by the device kind and the problem signature (n, stored entries, right-hand sides, shifts,
+precision).
 """
 
 import json
@@ -22,8 +23,12 @@ BLOCKS = (16, 24, 32, 40, 48)
 SHIFTS_PER_WG = (32, 64)
 
 
-def _key(H, n_rhs, n_shift, precision):
-    return f"n{H.n}_nnz{H.nnz}_K{n_rhs}_M{n_shift}_{precision}"
+def _key(H, n_rhs, n_shift, precision, device):
+    """The problem signature, prefixed by the device's architecture and compute-unit count (a
+    cache in a shared home directory may be read on another kind of GPU)."""
+    prop = torch.cuda.get_device_properties(device)
+    arch = getattr(prop, "gcnArchName", prop.name).split(":")[0]
+    return f"{arch}_cu{prop.multi_processor_count}_n{H.n}_nnz{H.nnz}_K{n_rhs}_M{n_shift}_{precision}"
 
 
 def _load(path):
@@ -38,7 +43,7 @@ def tune(H: "api.Hamiltonian", z, B: torch.Tensor, precision="fp64", iters=64, c
          blocks=BLOCKS, shifts_per_wg=SHIFTS_PER_WG, force=False, verbose=False):
     """Return {'block': T, 'shifts_per_wg': G, 'ms_per_iter': t} for this problem shape."""
     K, M = B.shape[0], len(z)
-    key = _key(H, K, M, precision)
+    key = _key(H, K, M, precision, B.device)
     table = _load(cache) if cache else {}
     if not force and key in table:
         return table[key]
