@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="diamond",
-                    choices=["diamond", "cubic", "hubbard", "batch", "krylov", "manybody"])
+                    choices=["diamond", "cubic", "hubbard", "batch", "krylov", "manybody", "gradient"])
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="default fp64 (fp32 storage for the batch workload)")
     ap.add_argument("--problems", type=int, default=8, help="lattices in the batch workload")
@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--n-shift", type=int, default=0)
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--columns", type=int, default=0,
+                    help="gradient workload: orbital columns (default all 16384), in batches of --n-rhs (256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8000)
     ap.add_argument("--variants", type=int, default=0,
@@ -763,6 +765,87 @@ def bench_batch(args, S, torch):
     return line
 
 
+def bench_gradient(args, S, torch):
+    """Band energy, its gradient with respect to every stored entry of H and the forces on the
+    atoms, on the 8x8x8 diamond cell (16384 orbitals): E = Re sum_q w_q z_q Tr G(z_q) over a
+    128-node contour (Fermi level 0, the circle through the Gershgorin bound - 1), every orbital
+    column solved by shifted COCG in batches of 256 right-hand sides (full solutions, whose
+    pair products give dE/dH_ab), then forces -dE/dR through t(r) = exp(-2 (r - r0)) by torch
+    autograd of the hopping values.  A step is the whole forward + gradient pass."""
+    from paper_0802_0748_amd.autograd import hopping_values
+    from workloads import config2_diamond
+    from workloads.lattices import diamond_entry_map, diamond_geometry
+
+    p = config2_diamond()
+    Hc, geo = p.H, p.extra
+    rows = np.repeat(np.arange(Hc.n), np.diff(Hc.row_ptr))
+    diag = np.zeros(Hc.n)
+    off = np.zeros(Hc.n)
+    isd = rows == Hc.col
+    diag[rows[isd]] = Hc.val[isd]
+    np.add.at(off, rows[~isd], np.abs(Hc.val[~isd]))
+    e_lo = float(np.min(diag - off)) - 1.0
+    nq = args.n_shift or 128
+    z, w = S.contour(e_lo, 0.0, nq)
+    cols = np.arange(args.columns or Hc.n, dtype=np.int64)
+    batch = args.n_rhs or 256
+    tol, max_iter = args.tol or 1e-8, args.max_iter or 60000
+    H = S.Hamiltonian.from_csr(Hc)
+    kind, bond, o1, o2 = diamond_entry_map(Hc, geo["bonds"])
+    _, bonds, vec0 = diamond_geometry(*geo["cells"])
+    t_ = lambda a: torch.from_numpy(np.asarray(a))
+    disp = t_(geo["displacement"].copy()).requires_grad_(True)
+    vals = hopping_values(t_(vec0), disp, t_(bonds), t_(geo["blocks"]), t_(kind), t_(bond), t_(o1), t_(o2),
+                          t_(Hc.val.copy()))
+    assert np.max(np.abs(vals.detach().numpy() - Hc.val)) < 1e-12
+    print(f"[bench] workload gradient: diamond n={Hc.n} nnz={Hc.nnz}, {nq}-node contour (min Im z "
+          f"{z.imag.min():.4f}), {len(cols)} columns in batches of {batch}", file=sys.stderr, flush=True)
+    S.density_matrix_energy(H, z[:4], w[:4], rhs_idx=cols[:2], want_grad=True, fixed_iter=32)
+    torch.cuda.synchronize()
+    S.set_profiling(True)
+    upd_ms = upd_bytes = upd_flops = 0.0
+    upd_launches = seed_iters = 0
+    t0 = time.perf_counter()
+    for st in range(args.steps):
+        ts = time.perf_counter()
+        E = 0.0
+        dE = torch.zeros(Hc.nnz, dtype=torch.float64, device="cuda")
+        for b0 in range(0, len(cols), batch):
+            out = S.density_matrix_energy(H, z, w, rhs_idx=cols[b0:b0 + batch], want_rho=False, want_grad=True,
+                                          tol=tol, max_iter=max_iter, allow_noconv=False)
+            t = S.last_timing()
+            upd_ms += t["update_ms"]
+            upd_bytes += t["update_bytes"]
+            upd_flops += t["update_flops"]
+            upd_launches += t["update_launches"]
+            seed_iters += t["iterations"]
+            E += out["E"].item()
+            dE += out["grad"]
+            if (b0 // batch) % 8 == 0:
+                print(f"[bench] step {st} columns {b0}..{b0 + batch - 1}: {time.perf_counter() - ts:.1f} s so far",
+                      file=sys.stderr, flush=True)
+        (g_disp,) = torch.autograd.grad(vals, disp, grad_outputs=dE.cpu())
+        forces = -g_disp
+        print(f"[bench] step {st}: {time.perf_counter() - ts:.2f} s, E = {E:.10f}, max |F| = "
+              f"{forces.abs().max().item():.3e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    S.set_profiling(False)
+    pairs = len(cols) * nq * args.steps
+    line = {
+        "metric": METRIC, "value": pairs / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"band energy + dE/dH + forces, diamond 8x8x8 (n={Hc.n}, nnz={Hc.nnz}), "
+                                f"{nq}-node contour with Fermi level 0, {len(cols)} orbital columns in batches of "
+                                f"{batch}, tol {tol:g}, max_iter {max_iter}"),
+                   "n": Hc.n, "nnz": int(Hc.nnz), "n_shift": nq, "n_rhs": int(len(cols)), "precision": "fp64",
+                   "block": 48, "energy": E, "max_force": float(forces.abs().max())},
+        "roofline": update_roofline(upd_ms, upd_bytes, upd_flops, upd_launches, "gradient", "fp64", ""),
+    }
+    return line
+
+
 def run_variants(S, torch, n_rhs):
     """The diamond problem with n_rhs right-hand sides solved by several forms of the solver."""
     from workloads import config2_diamond
@@ -835,6 +918,9 @@ def main():
         return 0
     if args.workload == "manybody":
         print(json.dumps(bench_manybody(args, S, torch)), flush=True)
+        return 0
+    if args.workload == "gradient":
+        print(json.dumps(bench_gradient(args, S, torch)), flush=True)
         return 0
     args.precision = args.precision or "fp64"
     p, desc = load_workload(args)

@@ -130,6 +130,9 @@ int hubbard_upload(int32_t L, int32_t n_up, int32_t n_dn, double t, double U, do
 
 int64_t csr_n(scocg_csr_t H);
 int64_t csr_nnz(scocg_csr_t H);
+/* Release the caller's handle.  Tapes recorded on H keep their own reference (backward() reads
+ * H's pattern), so the matrix lives until its last tape is freed too; H must not be used by the
+ * caller afterwards. */
 void csr_free(scocg_csr_t H);
 
 /*
@@ -288,12 +291,17 @@ int greens_diag_batched(int64_t n_problems, const scocg_csr_t *H, const int64_t 
  *     rho_ab = Re sum_q w_q G_ab(z_q),     E = Re sum_q w_q z_q sum_j G_jj(z_q)
  * for the columns j in rhs_idx (all n columns give the full rho on H's pattern
  * and the full band energy).  z, w: host, n_quad complex nodes and weights (see
- * scocg_contour).  Outputs (device, accumulated into, so zero them first):
- *   rho_nnz [nnz] or NULL: rho on the stored entries of H, CSR order (column j's entries)
+ * scocg_contour).  rhs_idx: host, n_rhs distinct columns in [0, n) (a repeated column is
+ * EINVAL: it would be counted twice).  Outputs (device, accumulated into, so zero them first):
+ *   rho_nnz [nnz] or NULL: rho on the stored entries of H, CSR order; column j adds its
+ *                          entries (a, j) (all columns give every entry of rho)
  *   E_band  [1]          : band energy contribution of the columns
  *   dE_dval [nnz] or NULL: derivative of E with respect to each stored entry,
- *                          Re sum_q w_q z_q sum_j x_qj[a] x_qj[b]
- * Right-hand sides are processed in batches of at most rhs_batch (0 = automatic).
+ *                          Re sum_q w_q z_q sum_j x_qj[a] x_qj[b] (any row length; the sums over
+ *                          pairs are taken in a fixed order)
+ * Right-hand sides are processed in batches of at most rhs_batch (0 = automatic: 256), each
+ * holding its full solutions (rhs_batch * n_quad * n complex numbers) while its products are
+ * formed.
  */
 int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double *z, const double *w, int64_t n_rhs,
                           const int64_t *rhs_idx, const scocg_opts *o, int64_t rhs_batch, double *rho_nnz,
@@ -309,6 +317,7 @@ int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double *z, const 
  *   grad_val device, [nnz] FP64, accumulated into (per stored CSR entry)
  */
 int backward(scocg_tape_t tape, const double *grad_G, double *grad_val, void *stream);
+/* Release a tape (its solutions and its reference to the matrix it was recorded on). */
 void tape_free(scocg_tape_t t);
 
 /*
@@ -341,6 +350,17 @@ typedef struct {
 int scocg_last_timing(scocg_timing *t);
 /* 1: record per-launch events around the update kernel (adds a small overhead). */
 void scocg_set_profiling(int on);
+
+/*
+ * Seed switches (Sec. 3.3) of right-hand side `rhs` in the most recent solve on this thread
+ * (shifted_cocg_solve, greens_diag, greens_diag_batched, greens_proj; for
+ * density_matrix_energy its last batch of right-hand sides).  Each entry is a pair
+ * (iterations completed when the old seed converged, index of the new seed shift), in the
+ * order they happened.  log: host array of 2 * max_entries int32, or NULL to only count.
+ * Returns the number of switches (entries beyond max_entries are not written), or -1 when
+ * rhs is outside the last solve's right-hand sides (message in scocg_last_error).
+ */
+int32_t scocg_last_switches(int64_t rhs, int32_t *log, int32_t max_entries);
 
 #ifdef __cplusplus
 }

@@ -187,7 +187,7 @@ def contour(e_lo: float, mu: float, n_quad: int):
     return c + R * e, wt * R * e / np.pi
 
 
-def density_matrix_energy(H, z, W, rhs_idx=None, **kw):
+def density_matrix_energy(H, z, W, rhs_idx=None, want_residuals=False, **kw):
     """Density matrix on the stored pattern of H and the band energy E = Tr[rho H].
 
     rho_ab = Re sum_k W_k G_ab(z_k) for every stored (a, b) (Sec. 2.1.1: only the
@@ -196,6 +196,8 @@ def density_matrix_energy(H, z, W, rhs_idx=None, **kw):
     accumulated (default: all).  Also returns dE/dH_ab, the exact derivative of
     the discrete band energy E = Re sum_k W_k z_k Tr G(z_k):
         dE/dH_ab = Re sum_k W_k z_k (G_k G_k)_ab = Re sum_k W_k z_k sum_j x_kj[a] x_kj[b].
+    want_residuals adds res_true[len(rhs_idx), M], the true residual of every solve
+    (Sec. 3.4), from which callers bound the error of these sums.
     """
     n = H.n
     z = np.asarray(z, dtype=np.complex128)
@@ -208,13 +210,20 @@ def density_matrix_energy(H, z, W, rhs_idx=None, **kw):
     E = 0.0
     in_set = np.zeros(n, dtype=bool)
     in_set[rhs_idx] = True
-    for j in rhs_idx:
+    res_true = np.zeros((len(rhs_idx), len(z))) if want_residuals else None
+    for c, j in enumerate(rhs_idx):
         out = shifted_cocg(H, z, unit(n, int(j)), **kw)
         X = out["X"]  # [M, n]: column j of G(z_k)
+        if want_residuals:
+            for k in range(len(z)):
+                res_true[c, k] = true_residual(H, z[k], X[k], unit(n, int(j)))
         # rho_ab for entries in column b = j: G_ab = X[k, a]
         sel = cols == j
         rho[sel] += np.real(W @ X[:, rows[sel]])
         E += float(np.real(np.sum(W * z * X[:, j])))
         # (G^2)_ab accumulates x_kj[a] x_kj[b] over all columns j
         grad += np.real((W * z) @ (X[:, rows] * X[:, cols]))
-    return dict(rho=rho, E=E, grad=grad)
+    out = dict(rho=rho, E=E, grad=grad)
+    if want_residuals:
+        out["res_true"] = res_true
+    return out

@@ -7,7 +7,7 @@ PyTorch used for device memory, streams and autograd.
 
 from .api import (Hamiltonian, Tape, backward, contour, csr_validate, density_matrix_energy, greens_diag,
                   greens_diag_batched, greens_diag_waves, greens_proj, ground_state, hubbard_fermion_op,
-                  krylov_greens_diag, krylov_greens_vec, last_timing, options, set_profiling, shifted_cocg_solve)
+                  krylov_greens_diag, krylov_greens_vec, last_switches, last_timing, options, set_profiling, shifted_cocg_solve)
 
 __all__ = [
     "Hamiltonian",
@@ -24,6 +24,7 @@ __all__ = [
     "hubbard_fermion_op",
     "krylov_greens_diag",
     "krylov_greens_vec",
+    "last_switches",
     "last_timing",
     "options",
     "set_profiling",

@@ -81,6 +81,7 @@ EXPORTED = [
     "scocg_last_error",
     "scocg_last_timing",
     "scocg_set_profiling",
+    "scocg_last_switches",
 ]
 
 _lib = None
@@ -144,6 +145,8 @@ def load():
     lib.scocg_last_timing.restype = i32
     lib.scocg_set_profiling.argtypes = [i32]
     lib.scocg_set_profiling.restype = None
+    lib.scocg_last_switches.argtypes = [i64, P, i32]
+    lib.scocg_last_switches.restype = ctypes.c_int32
     _lib = lib
     return lib
 

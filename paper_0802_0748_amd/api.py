@@ -125,10 +125,12 @@ class Hamiltonian:
 
 
 class Tape:
-    """Solutions kept by a solve for backward()."""
+    """Solutions kept by a solve for backward().  The library keeps the matrix the tape was
+    recorded on alive until the tape is freed; the tape also holds the Python Hamiltonian."""
 
-    def __init__(self, h, kind, n_shift, n_rhs, nnz):
+    def __init__(self, h, kind, n_shift, n_rhs, nnz, hamiltonian=None):
         self._h = h
+        self.hamiltonian = hamiltonian
         self.kind = kind
         self.nnz = nnz
         self.n_shift = n_shift
@@ -163,6 +165,21 @@ def last_timing() -> dict:
     t = C.Timing()
     C.load().scocg_last_timing(ctypes.byref(t))
     return {f: getattr(t, f) for f, _ in C.Timing._fields_}
+
+
+def last_switches(n_rhs: int) -> list:
+    """Seed switches of the last solve on this thread: for each right-hand side, the list of
+    (iterations completed when the old seed converged, new seed shift)."""
+    lib = C.load()
+    out = []
+    for j in range(int(n_rhs)):
+        c = lib.scocg_last_switches(j, None, 0)
+        if c < 0:
+            raise C.ScocgError(C.EINVAL, lib.scocg_last_error().decode())
+        buf = (ctypes.c_int32 * (2 * max(c, 1)))()
+        lib.scocg_last_switches(j, buf, c)
+        out.append([(int(buf[2 * e]), int(buf[2 * e + 1])) for e in range(c)])
+    return out
 
 
 def set_profiling(on: bool) -> None:
@@ -201,7 +218,7 @@ def shifted_cocg_solve(H: Hamiltonian, z, B: torch.Tensor, out: torch.Tensor = N
     rc = lib.shifted_cocg_solve(H.handle, M, zp, K, B.data_ptr(), ctypes.byref(o), out.data_ptr(), rep,
                                 ctypes.byref(tape) if o.keep_tape else None, _stream_ptr())
     C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
-    t = Tape(tape, "solve", M, K, H.nnz) if o.keep_tape and tape.value else None
+    t = Tape(tape, "solve", M, K, H.nnz, H) if o.keep_tape and tape.value else None
     return out, _report(rep, K, M), t, rc
 
 
@@ -219,7 +236,7 @@ def greens_diag(H: Hamiltonian, z, rhs_idx, allow_noconv=True, allow_breakdown=F
     rc = lib.greens_diag(H.handle, M, zp, K, idx.ctypes.data, ctypes.byref(o), G.data_ptr(), rep,
                          ctypes.byref(tape) if o.keep_tape else None, _stream_ptr())
     C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
-    t = Tape(tape, "greens", M, K, H.nnz) if o.keep_tape and tape.value else None
+    t = Tape(tape, "greens", M, K, H.nnz, H) if o.keep_tape and tape.value else None
     return G, _report(rep, K, M), t, rc
 
 

@@ -22,13 +22,21 @@ def _vals_host(vals: torch.Tensor) -> np.ndarray:
 
 
 class GreensDiag(torch.autograd.Function):
-    """G[k, c] = [(z_k - H(vals))^{-1}]_{jj}, j = rhs_idx[c]; differentiable in vals."""
+    """G[k, c] = [(z_k - H(vals))^{-1}]_{jj}, j = rhs_idx[c]; differentiable in vals.
+
+    A pair that stops unconverged raises (ScocgError with ENOCONV) unless opts has
+    allow_noconv=True; the per-pair report is available through the report argument."""
 
     @staticmethod
-    def forward(ctx, vals, H: "api.Hamiltonian", z, rhs_idx, opts):
+    def forward(ctx, vals, H: "api.Hamiltonian", z, rhs_idx, opts, report):
+        opts = dict(opts or {})
+        opts.setdefault("allow_noconv", False)
         H.update_values(_vals_host(vals))
-        G, rep, tape, rc = api.greens_diag(H, z, rhs_idx, keep_tape=True, **(opts or {}))
+        G, rep, tape, rc = api.greens_diag(H, z, rhs_idx, keep_tape=True, **opts)
+        if report is not None:
+            report.update(rep, rc=rc)
         ctx.tape = tape
+        ctx.hamiltonian = H
         ctx.nnz = H.nnz
         ctx.vals_device = vals.device
         ctx.report = rep
@@ -38,17 +46,20 @@ class GreensDiag(torch.autograd.Function):
     def backward(ctx, gG):
         grad = api.backward(ctx.tape, gG.to(torch.complex128).cuda())
         ctx.tape.close()
-        return grad.to(ctx.vals_device), None, None, None, None
+        return grad.to(ctx.vals_device), None, None, None, None, None
 
 
 class BandEnergy(torch.autograd.Function):
     """E = Re sum_q w_q z_q Tr G(z_q) over the contour nodes (zero temperature),
-    differentiable in vals: dE/dH_ab = Re sum_q w_q z_q (G_q G_q)_ab."""
+    differentiable in vals: dE/dH_ab = Re sum_q w_q z_q (G_q G_q)_ab.  Unconverged pairs raise
+    unless opts has allow_noconv=True."""
 
     @staticmethod
     def forward(ctx, vals, H: "api.Hamiltonian", z, w, opts):
+        opts = dict(opts or {})
+        opts.setdefault("allow_noconv", False)
         H.update_values(_vals_host(vals))
-        out = api.density_matrix_energy(H, z, w, rhs_idx=None, want_rho=False, want_grad=True, **(opts or {}))
+        out = api.density_matrix_energy(H, z, w, rhs_idx=None, want_rho=False, want_grad=True, **opts)
         ctx.save_for_backward(out["grad"])
         ctx.vals_device = vals.device
         return out["E"][0].to(vals.device)
@@ -59,8 +70,10 @@ class BandEnergy(torch.autograd.Function):
         return (gE.to(dE.device) * dE).to(ctx.vals_device), None, None, None, None
 
 
-def greens_diag(vals, H, z, rhs_idx, **opts):
-    return GreensDiag.apply(vals, H, z, rhs_idx, opts)
+def greens_diag(vals, H, z, rhs_idx, report=None, **opts):
+    """Differentiable G_jj(z_k).  report: optional dict that receives the per-pair report
+    (iters, status, residuals) and the status code of the solve."""
+    return GreensDiag.apply(vals, H, z, rhs_idx, opts, report)
 
 
 def band_energy(vals, H, z, w, **opts):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,6 +20,13 @@ namespace {
 
 thread_local std::string g_err;
 thread_local scocg_timing g_timing = {};
+// seed switches of the last solve on this thread: per rhs, (iterations done, new seed) pairs
+struct SwitchLog {
+    int64_t K = 0, M = 0;
+    std::vector<int32_t> count;  // [K]
+    std::vector<int32_t> log;    // [K][M][2]
+};
+thread_local SwitchLog g_swlog;
 int g_profiling = 0;
 
 int fail(int code, const std::string &msg)
@@ -121,16 +129,27 @@ struct PinnedBuf {
 
 }  // namespace
 
+// An uploaded matrix is shared by its owner (released with csr_free) and by every tape that
+// was recorded on it (released with tape_free): backward() reads its pattern, so the device
+// and host copies live until the last of them is released.
 struct scocg_csr {
     DevCSR d;
     std::vector<int64_t> h_row_ptr, h_col, h_ell_src;
     std::vector<double> h_val;
+    std::atomic<int> refs{1};
 };
 
+static void csr_release(scocg_csr *H);
+
 struct scocg_tape {
-    scocg_csr *H = nullptr;
+    scocg_csr *H = nullptr;  // holds a reference (released with the tape)
     int64_t K = 0, M = 0, n = 0;
     DevBuf X;  // [K][M][n] complex FP64
+    ~scocg_tape()
+    {
+        X.release();
+        if (H) csr_release(H);
+    }
 };
 
 // ------------------------------------------------------------------------------------------
@@ -170,7 +189,7 @@ extern "C" int scocg_csr_validate(int64_t n, int64_t nnz, const int64_t *rp, con
 static void free_dev(DevCSR &d)
 {
     void *ptrs[] = {d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.d_ell_pos, d.d_row_ptr, d.d_col, d.d_val,
-                    d.d_hub, d.d_hub_tables};
+                    d.d_mirror, d.d_hub, d.d_hub_tables};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     std::memset(&d, 0, sizeof(d));
@@ -246,6 +265,16 @@ extern "C" int csr_upload(int64_t n, int64_t nnz, const int64_t *rp, const int64
     d.trace = tr;
     std::vector<int32_t> col32(nnz);
     for (int64_t k = 0; k < nnz; ++k) col32[k] = (int32_t)col[k];
+    // position of the transposed entry (the pattern is symmetric when validated; an entry whose
+    // mirror is missing points at itself)
+    std::vector<int32_t> mirror(nnz);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t j = col[k];
+            const int64_t *b = col + rp[j], *e = col + rp[j + 1];
+            const int64_t *f = std::lower_bound(b, e, i);
+            mirror[k] = (int32_t)((f != e && *f == i) ? (f - col) : k);
+        }
     hipError_t e = hipSuccess;
     if ((e = upload(&d.d_slice_ptr, sptr.data(), sptr.size(), st)) != hipSuccess ||
         (e = upload(&d.d_slice_w, sw.data(), sw.size(), st)) != hipSuccess ||
@@ -253,6 +282,7 @@ extern "C" int csr_upload(int64_t n, int64_t nnz, const int64_t *rp, const int64
         (e = upload(&d.d_ell_val, eval.data(), eval.size(), st)) != hipSuccess ||
         (e = upload(&d.d_row_ptr, rp, (size_t)n + 1, st)) != hipSuccess ||
         (e = upload(&d.d_col, col32.data(), col32.size(), st)) != hipSuccess ||
+        (e = upload(&d.d_mirror, mirror.data(), mirror.size(), st)) != hipSuccess ||
         (e = upload(&d.d_val, val, (size_t)nnz, st)) != hipSuccess) {
         free_dev(d);
         delete H;
@@ -423,11 +453,18 @@ extern "C" int csr_update_values(scocg_csr_t H, const double *val, void *stream)
 extern "C" int64_t csr_n(scocg_csr_t H) { return H ? H->d.n : -1; }
 extern "C" int64_t csr_nnz(scocg_csr_t H) { return H ? H->d.nnz : -1; }
 
+static void csr_release(scocg_csr *H)
+{
+    if (H->refs.fetch_sub(1) == 1) {
+        free_dev(H->d);
+        delete H;
+    }
+}
+
 extern "C" void csr_free(scocg_csr_t H)
 {
     if (!H) return;
-    free_dev(H->d);
-    delete H;
+    csr_release(H);
 }
 
 extern "C" void scocg_default_opts(scocg_opts *o)
@@ -456,6 +493,22 @@ extern "C" int scocg_last_timing(scocg_timing *t)
 }
 
 extern "C" void scocg_set_profiling(int on) { g_profiling = on ? 1 : 0; }
+
+extern "C" int32_t scocg_last_switches(int64_t rhs, int32_t *log, int32_t max_entries)
+{
+    if (rhs < 0 || rhs >= g_swlog.K) {
+        g_err = "rhs out of range of the last solve";
+        return -1;
+    }
+    const int32_t c = g_swlog.count[rhs];
+    const int32_t stored = (int32_t)std::min<int64_t>(c, g_swlog.M);
+    if (log)
+        for (int32_t e = 0; e < std::min(stored, std::max(max_entries, 0)); ++e) {
+            log[2 * e + 0] = g_swlog.log[2 * (rhs * g_swlog.M + e) + 0];
+            log[2 * e + 1] = g_swlog.log[2 * (rhs * g_swlog.M + e) + 1];
+        }
+    return c;
+}
 
 // ------------------------------------------------------------------------------------------
 // the solver driver
@@ -580,6 +633,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     const size_t esz = o.precision == 0 ? sizeof(double2) : sizeof(float2);
 
     g_timing = scocg_timing{};
+    g_swlog.K = 0;
     TimerEvents tev;
     HIPCHK(tev.create());
     hipEvent_t ev_t0 = tev.t0, ev_t1 = tev.t1;
@@ -669,6 +723,8 @@ int solve(SolveRequest &rq, hipStream_t st)
     ALLOC(bcnt, K * sizeof(uint32_t));
     ALLOC(bsd, K * sizeof(int32_t));
     ALLOC(bstats, 3 * sizeof(unsigned long long));
+    DevBuf bswlog;
+    ALLOC(bswlog, KM * 2 * sizeof(int32_t));
     if (rq.unit_idx) ALLOC(bidx, K * sizeof(int64_t));
 
     s.z = bz.as<double2>();
@@ -705,6 +761,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.part1 = bp1.as<double>();
     s.cnt = bcnt.as<uint32_t>();
     s.stats = bstats.as<unsigned long long>();
+    s.swlog = bswlog.as<int32_t>();
     s.desc = bdesc.as<RhsDesc>();
 
     HIPCHK(hipMemcpyAsync(bdesc.ptr, hdesc.data(), K * sizeof(RhsDesc), hipMemcpyHostToDevice, st));
@@ -729,6 +786,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     HIPCHK(launch_zero(bnact.ptr, 2 * KM * sizeof(int32_t), st));
     HIPCHK(launch_zero(bblk.ptr, 2 * (size_t)K * 4 * sizeof(int32_t), st));
     HIPCHK(launch_zero(bstats.ptr, 3 * sizeof(unsigned long long), st));
+    HIPCHK(launch_zero(bswlog.ptr, KM * 2 * sizeof(int32_t), st));
     if (need_full) HIPCHK(launch_zero(s.X, (size_t)M * ntot * esz, st));
     HIPCHK(launch_zero(s.p, 2 * vec * sizeof(double2), st));
     HIPCHK(launch_init(s, rq.B, rq.unit_idx ? bidx.as<int64_t>() : nullptr, bsd.as<int32_t>(), limit, st));
@@ -908,7 +966,13 @@ int solve(SolveRequest &rq, hipStream_t st)
     HIPCHK(hipMemcpyAsync(h_res.data(), s.res, KM * sizeof(double), hipMemcpyDeviceToHost, st));
     unsigned long long h_stats[3] = {0, 0, 0};
     HIPCHK(hipMemcpyAsync(h_stats, s.stats, sizeof(h_stats), hipMemcpyDeviceToHost, st));
+    g_swlog.K = K;
+    g_swlog.M = M;
+    g_swlog.count.resize(K);
+    g_swlog.log.resize(KM * 2);
+    HIPCHK(hipMemcpyAsync(g_swlog.log.data(), s.swlog, KM * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    for (int64_t j = 0; j < K; ++j) g_swlog.count[j] = hs[j].switches;
     g_timing.update_bytes = (double)h_stats[0];
     g_timing.update_flops = (double)h_stats[2];
     float tot_ms = 0;
@@ -929,6 +993,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     }
     if ((o.check_true || o.refine > 0) && X64) {
         const scocg_timing saved = g_timing;
+        const SwitchLog saved_log = g_swlog;
         const int64_t gx = s.nblk;
         const int64_t *uidx = rq.unit_idx ? bidx.as<int64_t>() : nullptr;
         std::vector<double> h_nb(K);
@@ -998,6 +1063,7 @@ int solve(SolveRequest &rq, hipStream_t st)
             HIPCHK(hipMemcpyAsync(rq.keepX->ptr, rq.Xout, (size_t)M * ntot * sizeof(double2), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         g_timing = saved;
+        g_swlog = saved_log;
     }
     int rc = SCOCG_OK;
     for (size_t p = 0; p < KM; ++p) {
@@ -1047,6 +1113,7 @@ extern "C" int shifted_cocg_solve(scocg_csr_t H, int64_t n_shift, const double *
     int rc = solve(rq, (hipStream_t)stream);
     if (tp) {
         if (rc == SCOCG_OK || rc == SCOCG_ENOCONV) {
+            H->refs.fetch_add(1);
             tp->H = H;
             tp->K = n_rhs;
             tp->M = n_shift;
@@ -1456,6 +1523,7 @@ extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int6
     int rc = solve(rq, (hipStream_t)stream);
     if (tp) {
         if (rc == SCOCG_OK || rc == SCOCG_ENOCONV) {
+            H->refs.fetch_add(1);
             tp->H = H;
             tp->K = n_rhs;
             tp->M = n_shift;
@@ -1539,16 +1607,25 @@ extern "C" int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double
     const DevCSR &d = H->d;
     for (int64_t j = 0; j < n_rhs; ++j)
         if (rhs_idx[j] < 0 || rhs_idx[j] >= d.n) return fail(SCOCG_EINVAL, "rhs_idx out of range");
+    {
+        // each column's rho entries are written by one workgroup of its batch: a column listed
+        // twice would be accumulated twice (and, within one batch, by two racing workgroups)
+        std::vector<int64_t> sorted_idx(rhs_idx, rhs_idx + n_rhs);
+        std::sort(sorted_idx.begin(), sorted_idx.end());
+        if (std::adjacent_find(sorted_idx.begin(), sorted_idx.end()) != sorted_idx.end())
+            return fail(SCOCG_EINVAL, "rhs_idx lists a column more than once");
+    }
     int64_t maxrow = 0;
     for (int64_t i = 0; i < d.n; ++i) maxrow = std::max<int64_t>(maxrow, H->h_row_ptr[i + 1] - H->h_row_ptr[i]);
-    if (dE_dval && maxrow > 32) return fail(SCOCG_EINVAL, "dE_dval supports rows of at most 32 entries");
     hipStream_t st = (hipStream_t)stream;
     int64_t batch = rhs_batch > 0 ? rhs_batch : std::min<int64_t>(n_rhs, 256);
     batch = std::min(batch, n_rhs);
-    DevBuf bw, bz, bidx, bX, bEp, bc;
+    const int64_t nchunk = dE_dval ? pair_outer_chunks(d.n, batch * n_quad, (int)maxrow) : 0;
+    DevBuf bw, bz, bidx, bX, bEp, bc, bpart;
     if (bw.alloc(n_quad * sizeof(double2)) || bz.alloc(n_quad * sizeof(double2)) ||
         bidx.alloc(batch * sizeof(int64_t)) || bX.alloc((size_t)batch * n_quad * d.n * sizeof(double2)) ||
-        bEp.alloc(batch * sizeof(double)) || bc.alloc((size_t)batch * n_quad * sizeof(double2)))
+        bEp.alloc(batch * sizeof(double)) || bc.alloc((size_t)batch * n_quad * sizeof(double2)) ||
+        bpart.alloc((size_t)nchunk * (size_t)d.nnz * sizeof(double)))
         return fail(SCOCG_ENOMEM, "density_matrix_energy: device allocation failed");
     HIPCHK(hipMemcpyAsync(bw.ptr, w, n_quad * sizeof(double2), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bz.ptr, z, n_quad * sizeof(double2), hipMemcpyHostToDevice, st));
@@ -1571,11 +1648,12 @@ extern "C" int density_matrix_energy(scocg_csr_t H, int64_t n_quad, const double
         if (rc == SCOCG_ENOCONV) rc_all = SCOCG_ENOCONV;
         HIPCHK(hipMemcpyAsync(bidx.ptr, rhs_idx + j0, kb * sizeof(int64_t), hipMemcpyHostToDevice, st));
         HIPCHK(launch_density_rho(d.n, kb, n_quad, bX.as<double2>(), bidx.as<int64_t>(), d.d_row_ptr, d.d_col,
-                                  bw.as<double2>(), bz.as<double2>(), rho_nnz, bEp.as<double>(), E_band, st));
+                                  d.d_mirror, bw.as<double2>(), bz.as<double2>(), rho_nnz, bEp.as<double>(), E_band,
+                                  st));
         if (dE_dval) {
             HIPCHK(launch_pair_weights(0, kb, n_quad, bw.as<double2>(), bz.as<double2>(), nullptr, bc.as<double2>(), st));
             HIPCHK(launch_pair_outer(d.n, kb * n_quad, bX.as<double2>(), bc.as<double2>(), d.d_row_ptr, d.d_col,
-                                     (int)maxrow, dE_dval, st));
+                                     d.nnz, (int)maxrow, nchunk, bpart.as<double>(), dE_dval, st));
         }
         HIPCHK(hipStreamSynchronize(st));
     }
@@ -1593,13 +1671,15 @@ extern "C" int backward(scocg_tape_t tape, const double *grad_G, double *grad_va
     int64_t maxrow = 0;
     for (int64_t i = 0; i < d.n; ++i)
         maxrow = std::max<int64_t>(maxrow, tape->H->h_row_ptr[i + 1] - tape->H->h_row_ptr[i]);
-    if (maxrow > 32) return fail(SCOCG_EINVAL, "backward supports rows of at most 32 entries");
     hipStream_t st = (hipStream_t)stream;
-    DevBuf bc;
-    if (bc.alloc((size_t)tape->K * tape->M * sizeof(double2))) return fail(SCOCG_ENOMEM, "backward: allocation failed");
+    const int64_t npairs = tape->K * tape->M;
+    const int64_t nchunk = pair_outer_chunks(d.n, npairs, (int)maxrow);
+    DevBuf bc, bpart;
+    if (bc.alloc((size_t)npairs * sizeof(double2)) || bpart.alloc((size_t)nchunk * (size_t)d.nnz * sizeof(double)))
+        return fail(SCOCG_ENOMEM, "backward: allocation failed");
     HIPCHK(launch_pair_weights(1, tape->K, tape->M, nullptr, nullptr, (const double2 *)grad_G, bc.as<double2>(), st));
-    HIPCHK(launch_pair_outer(d.n, tape->K * tape->M, tape->X.as<double2>(), bc.as<double2>(), d.d_row_ptr, d.d_col,
-                             (int)maxrow, grad_val, st));
+    HIPCHK(launch_pair_outer(d.n, npairs, tape->X.as<double2>(), bc.as<double2>(), d.d_row_ptr, d.d_col, d.nnz,
+                             (int)maxrow, nchunk, bpart.as<double>(), grad_val, st));
     HIPCHK(hipStreamSynchronize(st));
     return SCOCG_OK;
 }

@@ -1022,6 +1022,10 @@ __global__ void __launch_bounds__(WG) k_block_finalize(SolveDev s)
         w->inv_ppt = cdiv(cmk(1, 0), ppt);
         w->sw_target = t;
         w->switches = st.switches + 1;
+        if (st.switches < s.M) {
+            s.swlog[2 * (j * s.M + st.switches) + 0] = st.iter;
+            s.swlog[2 * (j * s.M + st.switches) + 1] = t;
+        }
     }
 }
 
@@ -1193,12 +1197,16 @@ __global__ void k_gather_diag(const RhsDesc *__restrict__ desc, int64_t K, int64
 }
 
 // Density matrix, band energy and energy gradient of one batch of columns.
-//   rho[e] += Re sum_k w_k x_{j,k}[col(e)]     for stored entries e of row cols_of_rhs[j]
-//   Epart[j] = Re sum_k w_k z_k x_{j,k}[cols_of_rhs[j]]
+//   rho[(a, b)] += Re sum_k w_k x_{j,k}[a]     for the stored entries (a, b) of column b = cols_of_rhs[j]
+//   Epart[j] = Re sum_k w_k z_k x_{j,k}[b]
+// Column b's entries are found through row b's (the pattern is symmetric): entry e = (b, a) of
+// row b names a, and its mirror is the position of (a, b).  Each column's entries are its own,
+// so the workgroups of a batch (distinct columns) never write the same entry.
 __global__ void k_density_rho(int64_t n, int64_t K, int64_t M, const double2 *__restrict__ X,
                               const int64_t *__restrict__ cols_of_rhs, const int64_t *__restrict__ row_ptr,
-                              const int32_t *__restrict__ col, const double2 *__restrict__ w,
-                              const double2 *__restrict__ z, double *__restrict__ rho, double *__restrict__ Epart)
+                              const int32_t *__restrict__ col, const int32_t *__restrict__ mirror,
+                              const double2 *__restrict__ w, const double2 *__restrict__ z, double *__restrict__ rho,
+                              double *__restrict__ Epart)
 {
     const int64_t j = blockIdx.x;
     const int64_t b = cols_of_rhs[j];
@@ -1210,7 +1218,7 @@ __global__ void k_density_rho(int64_t n, int64_t K, int64_t M, const double2 *__
             const double2 x = X[(j * M + k) * n + a];
             acc += w[k].x * x.x - w[k].y * x.y;
         }
-        if (rho) rho[e] += acc;
+        if (rho) rho[mirror[e]] += acc;
     }
     if (threadIdx.x == 0) {
         double acc = 0;
@@ -1232,25 +1240,35 @@ __global__ void k_sum_into(const double *__restrict__ part, int64_t count, doubl
     }
 }
 
-// grad[e] += Re sum_p c_p x_p[a] x_p[b] for every stored entry e = (a, b); one thread per row a.
-// c_p is given per (rhs, shift) pair.  MAXW bounds the row length held in registers.
+// Partial sums of the pair contraction Re sum_p c_p x_p[a] x_p[b] over the stored entries
+// e = (a, b) (the energy gradient and the adjoint of G, which needs no second solve because
+// z - H is complex symmetric).  Work item: one row a, one segment of at most MAXW of its
+// entries, one chunk of pairs; grid (row tiles of 256, segments, chunks).  Each item writes
+// part[chunk][e] for its entries; k_chunk_sum adds the chunks in order, so the result does not
+// depend on scheduling.  Per pair the 256 rows of a tile read x_p[a] contiguously and gather
+// x_p[b] from the same pair vector (L2-resident for the tile's neighbourhood).
 template <int MAXW>
-__global__ void __launch_bounds__(WG) k_pair_outer(int64_t n, int64_t npairs, const double2 *__restrict__ X,
-                                                   const double2 *__restrict__ c, const int64_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ col, double *__restrict__ grad)
+__global__ void __launch_bounds__(WG) k_pair_outer(int64_t n, int64_t npairs, int64_t pch,
+                                                   const double2 *__restrict__ X, const double2 *__restrict__ c,
+                                                   const int64_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, int64_t nnz,
+                                                   double *__restrict__ part)
 {
     const int64_t a = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (a >= n) return;
-    const int64_t e0 = row_ptr[a];
-    const int w = (int)(row_ptr[a + 1] - e0);
+    const int64_t seg0 = row_ptr[a] + (int64_t)blockIdx.y * MAXW;
+    const int w = (int)min((int64_t)MAXW, row_ptr[a + 1] - seg0);
+    if (w <= 0) return;
+    const int64_t p0 = (int64_t)blockIdx.z * pch;
+    const int64_t p1 = min(npairs, p0 + pch);
     int cols[MAXW];
     double acc[MAXW];
 #pragma unroll
     for (int i = 0; i < MAXW; ++i) {
-        cols[i] = (i < w) ? col[e0 + i] : 0;
+        cols[i] = (i < w) ? col[seg0 + i] : 0;
         acc[i] = 0;
     }
-    for (int64_t p = 0; p < npairs; ++p) {
+    for (int64_t p = p0; p < p1; ++p) {
         const double2 *x = X + p * n;
         const double2 xa = cmul(c[p], x[a]);
 #pragma unroll
@@ -1261,9 +1279,20 @@ __global__ void __launch_bounds__(WG) k_pair_outer(int64_t n, int64_t npairs, co
             }
         }
     }
+    double *out = part + (int64_t)blockIdx.z * nnz + seg0;
 #pragma unroll
     for (int i = 0; i < MAXW; ++i)
-        if (i < w) grad[e0 + i] += acc[i];
+        if (i < w) out[i] = acc[i];
+}
+
+// grad[e] += sum over chunks, in chunk order
+__global__ void k_chunk_sum(int64_t nnz, int64_t nchunk, const double *__restrict__ part, double *__restrict__ grad)
+{
+    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (e >= nnz) return;
+    double acc = 0;
+    for (int64_t c = 0; c < nchunk; ++c) acc += part[c * nnz + e];
+    grad[e] += acc;
 }
 
 // per-pair weights for the band-energy derivative: c_p = w_k z_k for pair p = (j, k)
@@ -1412,11 +1441,11 @@ hipError_t launch_gather_diag(const SolveDev &s, const int64_t *rows, double2 *G
 
 // Observable kernels used by the host driver directly.
 hipError_t launch_density_rho(int64_t n, int64_t K, int64_t M, const double2 *X, const int64_t *cols_of_rhs,
-                              const int64_t *row_ptr, const int32_t *col, const double2 *w, const double2 *z,
-                              double *rho, double *Epart, double *Eacc, hipStream_t st)
+                              const int64_t *row_ptr, const int32_t *col, const int32_t *mirror, const double2 *w,
+                              const double2 *z, double *rho, double *Epart, double *Eacc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_density_rho, dim3((unsigned)K), dim3(64), 0, st, n, K, M, X, cols_of_rhs, row_ptr, col, w,
-                       z, rho, Epart);
+    hipLaunchKernelGGL(k_density_rho, dim3((unsigned)K), dim3(64), 0, st, n, K, M, X, cols_of_rhs, row_ptr, col,
+                       mirror, w, z, rho, Epart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, st, Epart, K, Eacc);
@@ -1432,14 +1461,50 @@ hipError_t launch_pair_weights(int mode, int64_t K, int64_t M, const double2 *w,
     return hipGetLastError();
 }
 
-hipError_t launch_pair_outer(int64_t n, int64_t npairs, const double2 *X, const double2 *c, const int64_t *row_ptr,
-                             const int32_t *col, int max_row, double *grad, hipStream_t st)
+// Segment width and count for the longest row: rows of up to 8 or 20 entries take one
+// segment of that width, longer rows segments of 32.
+static void pair_outer_shape(int max_row, int &maxw, int64_t &nseg)
 {
-    const dim3 g((unsigned)((n + WG - 1) / WG));
-    if (max_row <= 8) hipLaunchKernelGGL(k_pair_outer<8>, g, dim3(WG), 0, st, n, npairs, X, c, row_ptr, col, grad);
-    else if (max_row <= 20) hipLaunchKernelGGL(k_pair_outer<20>, g, dim3(WG), 0, st, n, npairs, X, c, row_ptr, col, grad);
-    else if (max_row <= 32) hipLaunchKernelGGL(k_pair_outer<32>, g, dim3(WG), 0, st, n, npairs, X, c, row_ptr, col, grad);
-    else return hipErrorInvalidValue;
+    maxw = max_row <= 8 ? 8 : (max_row <= 20 ? 20 : 32);
+    nseg = max_row <= 0 ? 1 : (max_row + maxw - 1) / maxw;
+}
+
+int64_t pair_outer_chunks(int64_t n, int64_t npairs, int max_row)
+{
+    int maxw;
+    int64_t nseg;
+    pair_outer_shape(max_row, maxw, nseg);
+    const int64_t tiles = (n + WG - 1) / WG;
+    // about 2048 workgroups fill the 256 compute units several times over
+    int64_t nchunk = (2048 + tiles * nseg - 1) / (tiles * nseg);
+    nchunk = nchunk < 1 ? 1 : nchunk;
+    nchunk = nchunk > npairs ? npairs : nchunk;
+    nchunk = nchunk > 65535 ? 65535 : nchunk;
+    return nchunk < 1 ? 1 : nchunk;
+}
+
+hipError_t launch_pair_outer(int64_t n, int64_t npairs, const double2 *X, const double2 *c, const int64_t *row_ptr,
+                             const int32_t *col, int64_t nnz, int max_row, int64_t nchunk, double *part, double *grad,
+                             hipStream_t st)
+{
+    if (npairs <= 0 || nnz <= 0) return hipSuccess;
+    int maxw;
+    int64_t nseg;
+    pair_outer_shape(max_row, maxw, nseg);
+    if (nseg > 65535 || nchunk < 1 || nchunk > 65535) return hipErrorInvalidValue;
+    const int64_t pch = (npairs + nchunk - 1) / nchunk;
+    const dim3 g((unsigned)((n + WG - 1) / WG), (unsigned)nseg, (unsigned)nchunk);
+    // every chunk writes every stored entry (each lies in exactly one segment of its row)
+    if (maxw == 8)
+        hipLaunchKernelGGL(k_pair_outer<8>, g, dim3(WG), 0, st, n, npairs, pch, X, c, row_ptr, col, nnz, part);
+    else if (maxw == 20)
+        hipLaunchKernelGGL(k_pair_outer<20>, g, dim3(WG), 0, st, n, npairs, pch, X, c, row_ptr, col, nnz, part);
+    else
+        hipLaunchKernelGGL(k_pair_outer<32>, g, dim3(WG), 0, st, n, npairs, pch, X, c, row_ptr, col, nnz, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)((nnz + WG - 1) / WG)), dim3(WG), 0, st, nnz, nchunk,
+                       (const double *)part, grad);
     return hipGetLastError();
 }
 

@@ -103,6 +103,7 @@ struct DevCSR {
     int32_t *d_ell_pos;   // [ell_nnz] CSR position of each slot (-1 padding)
     int64_t *d_row_ptr;   // [n+1] CSR pattern (int64)
     int32_t *d_col;       // [nnz]
+    int32_t *d_mirror;    // [nnz] CSR position of the transposed entry (a, b) -> (b, a)
     double *d_val;        // [nnz] CSR values
     double trace;         // Tr(H) (host side)
     int64_t *h_row_ptr;   // host copies of the pattern (for value updates)
@@ -178,6 +179,8 @@ struct SolveDev {
     int64_t hub_du_max;        // largest number of up-spin configurations among them
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs,
                                // [2] its algorithmic flops
+    int32_t *swlog;            // [K][M][2] seed switches of each rhs: (iterations done, new seed shift);
+                               // a shift becomes the seed at most once, so M entries suffice
 };
 
 hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_idx,
@@ -200,11 +203,15 @@ hipError_t launch_add_correction(int64_t n, const int64_t *pair_list, int64_t co
                                  hipStream_t st);
 hipError_t launch_gather_diag(const SolveDev &s, const int64_t *rows, double2 *G, hipStream_t st);
 hipError_t launch_density_rho(int64_t n, int64_t K, int64_t M, const double2 *X, const int64_t *cols_of_rhs,
-                              const int64_t *row_ptr, const int32_t *col, const double2 *w, const double2 *z,
-                              double *rho, double *Epart, double *Eacc, hipStream_t st);
+                              const int64_t *row_ptr, const int32_t *col, const int32_t *mirror, const double2 *w,
+                              const double2 *z, double *rho, double *Epart, double *Eacc, hipStream_t st);
 hipError_t launch_pair_weights(int mode, int64_t K, int64_t M, const double2 *w, const double2 *z,
                                const double2 *g, double2 *c, hipStream_t st);
+// grad[e] += Re sum_p c_p x_p[a] x_p[b] over the stored entries e = (a, b) of the CSR pattern,
+// through part ([nchunk][nnz] doubles, nchunk from pair_outer_chunks).
+int64_t pair_outer_chunks(int64_t n, int64_t npairs, int max_row);
 hipError_t launch_pair_outer(int64_t n, int64_t npairs, const double2 *X, const double2 *c, const int64_t *row_ptr,
-                             const int32_t *col, int max_row, double *grad, hipStream_t st);
+                             const int32_t *col, int64_t nnz, int max_row, int64_t nchunk, double *part, double *grad,
+                             hipStream_t st);
 
 }  // namespace scocg

@@ -24,15 +24,10 @@ def _S():
     return S
 
 
-def _cpu_true_residual(H, z, x, b):
-    A = H.to_scipy()
-    r = b - (z * x - A @ x)
-    return np.linalg.norm(r) / np.linalg.norm(b)
-
-
-def test_diamond_bench_configuration():
-    """Diamond 8x8x8 (16384 rows), 256 shifts x 256 unit RHS, FP64, tol 1e-8: every pair
-    converges; true residuals at the tolerance; sampled pairs agree with plain COCG."""
+@pytest.fixture(scope="module")
+def diamond_run():
+    """The diamond benchmark solve (16384 rows, 256 shifts x 256 unit RHS, FP64, tol 1e-8, the
+    default 48-iteration blocks and overlapped schedule), kept on the device for the checks."""
     S = _S()
     p = config2_diamond()
     H = S.Hamiltonian.from_csr(p.H)
@@ -42,21 +37,94 @@ def test_diamond_bench_configuration():
     t0 = time.perf_counter()
     X, rep, _, rc = S.shifted_cocg_solve(H, p.z, B, tol=1e-8, max_iter=40000, check_true=True)
     torch.cuda.synchronize()
+    logs = S.last_switches(K)
     print(f"diamond full solve {time.perf_counter() - t0:.1f} s, switches {S.last_timing()['switches']}, "
           f"max true residual {rep['res_true'].max():.2e}", flush=True)
-    assert rc == 0
+    yield dict(p=p, X=X, rep=rep, rc=rc, logs=logs)
+    del X
+
+
+def test_diamond_bench_configuration(diamond_run):
+    """Every one of the 65,536 pairs converges and its FP64 true residual (GPU) is at the
+    tolerance."""
+    rep = diamond_run["rep"]
+    assert diamond_run["rc"] == 0
     assert np.all(rep["status"] == 0)
     assert rep["res_true"].max() < 20 * 1e-8
-    rng = np.random.default_rng(0)
-    for j, k in [(0, 128), (int(rng.integers(K)), int(rng.integers(M)))]:
-        x_gpu = X[j, k].cpu().numpy()
+    assert sum(len(l) for l in diamond_run["logs"]) > 0
+
+
+def _sampled_pairs(run, n_random, seed=0):
+    p, logs = run["p"], run["logs"]
+    K, M = p.n_rhs, len(p.z)
+    pairs = {(j, t) for j in range(K) for _, t in logs[j]}  # every shift that served as a seed
+    rng = np.random.default_rng(seed)
+    while len(pairs) < len({(j, t) for j in range(K) for _, t in logs[j]}) + n_random:
+        pairs.add((int(rng.integers(K)), int(rng.integers(M))))
+    return sorted(pairs)
+
+
+def test_diamond_cpu_true_residuals_of_sampled_pairs(diamond_run):
+    """CPU (scipy, FP64) true residuals ||b - (z - H) x|| of more than 1024 pairs: every shift
+    that became a seed after a switch plus random pairs.  Each is at the tolerance and agrees
+    with the residual the GPU reported for it."""
+    p, X, rep = diamond_run["p"], diamond_run["X"], diamond_run["rep"]
+    A = p.H.to_scipy()
+    pairs = _sampled_pairs(diamond_run, 1024)
+    assert len(pairs) > 1024
+    by_rhs = {}
+    for j, k in pairs:
+        by_rhs.setdefault(j, []).append(k)
+    worst = 0.0
+    for j, ks in by_rhs.items():
+        xs = X[j, ks].cpu().numpy()  # [m, n]
+        b = O.unit(p.H.n, int(p.rhs_idx[j]))
+        ax = (A @ xs.T).T
+        r = b[None, :] - (p.z[ks][:, None] * xs - ax)
+        res = np.linalg.norm(r, axis=1)
+        worst = max(worst, float(res.max()))
+        g = rep["res_true"][j, ks]
+        assert np.all(np.abs(res - g) <= 1e-6 * res + 1e-14), (j, ks)
+    print(f"{len(pairs)} sampled pairs: max CPU true residual {worst:.2e}", flush=True)
+    assert worst < 20 * 1e-8
+
+
+def test_diamond_oracle_single_pair_solves(diamond_run):
+    """Eight pairs against plain FP64 COCG from the oracle (tolerance-stopped, run in parallel
+    threads): the slowest pairs (shifts nearest the spectral centre Tr(H)/n, which need the most
+    iterations), a shift that became a seed after a switch, and random pairs.  Two converged
+    answers differ by at most the sum of their residual bounds (Sec. 3.4)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    p, X, rep, logs = diamond_run["p"], diamond_run["X"], diamond_run["rep"], diamond_run["logs"]
+    K, M, n = p.n_rhs, len(p.z), p.H.n
+    centre = p.H.diagonal().sum() / n
+    near = np.argsort(np.abs(p.z.real - centre))[:3]
+    slow = np.unravel_index(np.argsort(rep["iters"], axis=None)[-2:], rep["iters"].shape)
+    rng = np.random.default_rng(1)
+    picks = [(int(rng.integers(K)), int(k)) for k in near]
+    picks += [(int(a), int(b)) for a, b in zip(*slow)]
+    jsw = next(j for j in range(K) if logs[j])
+    picks.append((jsw, logs[jsw][-1][1]))
+    picks += [(0, 128), (int(rng.integers(K)), int(rng.integers(M)))]
+    assert len(set(picks)) == 8
+
+    def one(pair):
+        j, k = pair
         b = O.unit(n, int(p.rhs_idx[j]))
-        assert _cpu_true_residual(p.H, p.z[k], x_gpu, b) < 20 * 1e-8
-        ref = O.cocg(p.H, p.z[k], b, tol=1e-8, max_iter=60000)
+        ref = O.cocg(p.H, p.z[k], b, tol=1e-8, max_iter=80000)
+        return pair, ref, O.true_residual(p.H, p.z[k], ref["x"], b)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        results = list(ex.map(one, picks))
+    print(f"8 oracle single-pair solves: {time.perf_counter() - t0:.1f} s, iterations "
+          f"{[r[1]['iters'] for r in results]} vs GPU {[int(rep['iters'][j, k]) for j, k in picks]}", flush=True)
+    for (j, k), ref, r_orc in results:
         assert ref["status"] == 0
-        r_orc = O.true_residual(p.H, p.z[k], ref["x"], b)
+        x_gpu = X[j, k].cpu().numpy()
         bound = (rep["res_true"][j, k] + r_orc) / p.z[k].imag
-        assert np.linalg.norm(x_gpu - ref["x"]) <= bound * (1 + 1e-6)
+        assert np.linalg.norm(x_gpu - ref["x"]) <= bound * (1 + 1e-6), (j, k)
 
 
 def test_hubbard_full_size():
@@ -78,16 +146,25 @@ def test_hubbard_full_size():
           flush=True)
     assert rc == 0
     assert rep["res_true"].max() < 20 * 1e-8
-    for k in (0, 64, 127):
+    # CPU true residuals of all 128 shifts (the oracle's FP64 residual routine, 16 threads)
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(k):
         x = X[0, k].cpu().numpy()
-        assert _cpu_true_residual(p.H, p.z[k], x, p.B[0]) < 20 * 1e-8
+        return O.true_residual(p.H, p.z[k], x, p.B[0])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        res = np.array(list(ex.map(one, range(len(p.z)))))
+    print(f"CPU true residuals of {len(res)} shifts in {time.perf_counter() - t0:.1f} s: max {res.max():.2e}",
+          flush=True)
+    assert np.all(res < 20 * 1e-8)
+    assert np.all(np.abs(res - rep["res_true"][0]) <= 1e-6 * res + 1e-14)
 
 
-def test_diamond_fp32_storage_error_is_stated_per_result():
-    """FP32 storage at the benchmark's size (64 of its right-hand sides): each result's FP64
-    true residual bounds its distance to the FP64 solve (Sec. 3.4), so the report states the
-    error of every result; and the error stays within 1e-4 relative (the FP32 form's
-    rounding over 22,000-34,000 iterations; small problems meet 1e-5)."""
+@pytest.fixture(scope="module")
+def fp32_run():
+    """64 of the diamond benchmark's right-hand sides solved with FP64 and with FP32 storage."""
     S = _S()
     p = config2_diamond(n_rhs=64)
     H = S.Hamiltonian.from_csr(p.H)
@@ -97,14 +174,44 @@ def test_diamond_fp32_storage_error_is_stated_per_result():
     X64, rep64, _, rc64 = S.shifted_cocg_solve(H, p.z, B, tol=1e-8, max_iter=40000, check_true=True)
     X32, rep32, _, rc32 = S.shifted_cocg_solve(H, p.z, B, tol=1e-8, max_iter=40000, check_true=True,
                                                precision="fp32")
-    assert rc64 == 0 and rc32 == 0
     diff = torch.linalg.vector_norm(X32 - X64, dim=2).cpu().numpy()
     norm = torch.linalg.vector_norm(X64, dim=2).cpu().numpy()
-    bound = (rep32["res_true"] + rep64["res_true"]) / p.z.imag[None, :]
     print(f"diamond fp32: max rel diff {np.max(diff / norm):.2e}, max true residual {rep32['res_true'].max():.2e}",
           flush=True)
-    assert np.all(diff <= bound * (1 + 1e-6))
-    assert np.max(diff / norm) < 1e-4
+    yield dict(p=p, H=H, B=B, X64=X64, rep64=rep64, rc64=rc64, rep32=rep32, rc32=rc32, diff=diff, norm=norm)
+
+
+def test_diamond_fp32_storage_error_is_stated_per_result(fp32_run):
+    """FP32 storage at the benchmark's size: each result's FP64 true residual bounds its distance
+    to the FP64 solve (Sec. 3.4), so the report states the error of every result."""
+    r = fp32_run
+    assert r["rc64"] == 0 and r["rc32"] == 0
+    bound = (r["rep32"]["res_true"] + r["rep64"]["res_true"]) / r["p"].z.imag[None, :]
+    assert np.all(r["diff"] <= bound * (1 + 1e-6))
+
+
+@pytest.mark.xfail(strict=False, reason="FP32 storage of x_k and u_k accumulates about 6e-5 relative error over the "
+                   "22,000-34,000 iterations of the diamond problem; the 1e-5 target holds on small problems and with "
+                   "FP64 refinement, not for plain FP32 storage at this size")
+def test_diamond_fp32_storage_meets_1e5(fp32_run):
+    """The FP32-storage target: within 1e-5 of the FP64 solve, relative, per result."""
+    r = fp32_run
+    assert np.max(r["diff"] / r["norm"]) < 1e-5
+
+
+def test_diamond_fp32_storage_with_refinement_meets_1e5(fp32_run):
+    """FP32 storage followed by the FP64 true-residual refinement: every result within 1e-5 of
+    the FP64 solve, relative (eight of the right-hand sides)."""
+    S = _S()
+    r = fp32_run
+    p, B = r["p"], r["B"][:8]
+    X, rep, _, rc = S.shifted_cocg_solve(r["H"], p.z, B, tol=1e-8, max_iter=40000, precision="fp32", refine=2)
+    assert rc == 0
+    assert rep["res_true"].max() <= 1e-8
+    diff = torch.linalg.vector_norm(X - r["X64"][:8], dim=2).cpu().numpy()
+    rel = diff / r["norm"][:8]
+    print(f"diamond fp32 + refinement: max rel diff {rel.max():.2e}", flush=True)
+    assert rel.max() < 1e-5
 
 
 def test_ground_state_at_the_papers_dimension():

@@ -46,6 +46,45 @@ def test_fixed_iteration_fp64_matches_oracle(n):
         assert np.all(rep["iters"][j] == iters)
 
 
+@pytest.mark.parametrize("iters", [96, 144])
+def test_fixed_iteration_long_blocks_match_oracle(iters):
+    """The production update (48-iteration blocks, the LDS-staged kernel with up to 64 shifts per
+    workgroup) against the oracle over two and three full blocks: 1728 rows (a ragged last
+    64-row tile), 70 shifts (a full group of 64 and a ragged one of 6), three dense right-hand
+    sides.  The shifts lie just below the spectrum (Re z = lambda_min - 0.003 .. 0.3), where the
+    shifted matrices are close to definite and COCG converges smoothly, so rounding is not
+    amplified over a hundred iterations and only summation order and fused multiply-adds
+    differ.  (At interior energies COCG's residual peaks amplify rounding: the oracle itself,
+    started from another seed, moves by 6e-4 after 96 iterations there, which is why
+    tolerance-stopped interior runs are compared through the residual bound.)"""
+    S = _S()
+    rng = np.random.default_rng(96)
+    L = 12
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    lmin = np.linalg.eigvalsh(Hc.to_dense())[0]
+    M = 70
+    r2 = np.random.default_rng(5)
+    z = lmin - np.linspace(0.003, 0.3, M) + 1j * r2.uniform(0.003, 0.03, M)
+    B = r2.normal(size=(3, Hc.n)) + 1j * r2.normal(size=(3, Hc.n))
+    H = S.Hamiltonian.from_csr(Hc)
+    Bt = torch.from_numpy(B).cuda()
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, fixed_iter=iters, block=48)
+    assert rc == 0 and np.all(rep["iters"] == iters)
+    Xg = X.cpu().numpy()
+    # the later blocks do change the solutions well above the comparison bar
+    X1, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=48, block=48)
+    change = np.linalg.norm(Xg - X1.cpu().numpy(), axis=2) / np.linalg.norm(Xg, axis=2)
+    assert np.median(change) > 1e-7
+    worst = 0.0
+    for j in range(3):
+        ref = O.shifted_cocg(Hc, z, B[j], fixed_iter=iters, seed_index=O.default_seed(Hc, z))
+        for k in range(M):
+            worst = max(worst, _rel(Xg[j, k], ref["X"][k]))
+    print(f"{iters} iterations in blocks of 48: max relative difference {worst:.2e}, median change after the "
+          f"first block {np.median(change):.1e}")
+    assert worst < 1e-10
+
+
 def test_block_length_does_not_change_bits():
     """The deferred shift update applies the same operations in the same order for any block length."""
     S = _S()
@@ -230,6 +269,12 @@ def test_production_switching_short_run_matches_oracle():
         assert np.all(rep["res_true"][j] < 20 * tol)
     assert n_sw >= 2 and t["switches"] == n_sw
     assert n_equal >= len(z)
+    # the switch logs: the same switches, after the same iteration, to the same new seed (the
+    # oracle logs the 0-based index of the iteration after which it switched)
+    logs = S.last_switches(2)
+    for j in range(2):
+        ref = O.shifted_cocg(Hc, z, B[j], tol=tol, max_iter=5000, seed_index=13)
+        assert logs[j] == [(it + 1, t_) for it, t_ in ref["switches"]], (j, logs[j], ref["switches"])
 
 
 def test_production_switching_long_run_within_residual_bound():
@@ -249,15 +294,52 @@ def test_production_switching_long_run_within_residual_bound():
     X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=tol, max_iter=5000, seed_index=13,
                                          check_true=True)
     assert rc == 0 and S.last_timing()["switches"] >= 1
+    logs = S.last_switches(2)
     Xg = X.cpu().numpy()
     for j in range(2):
         ref = O.shifted_cocg(Hc, z, B[j], tol=tol, max_iter=5000, seed_index=13)
         assert ref["ret"] == 0
         assert np.all(np.abs(rep["iters"][j] - ref["iters"]) <= 0.1 * ref["iters"] + 2)
+        # same new seeds in the same order; the iteration of each switch is a freeze decision,
+        # which rounding moves by a few iterations on long runs
+        assert [t_ for _, t_ in logs[j]] == [t_ for _, t_ in ref["switches"]], (j, logs[j], ref["switches"])
+        for (ig, _), (io, _) in zip(logs[j], ref["switches"]):
+            assert abs(ig - (io + 1)) <= 0.06 * (io + 1) + 2
         for k in range(len(z)):
             d, bound = _bound_check(Hc, z[k], B[j], Xg[j, k], rep["res_true"][j, k], ref["X"][k])
             assert d <= bound, (j, k, d, bound)
             assert rep["res_true"][j, k] < 20 * tol
+
+
+@pytest.mark.parametrize("block", [1, 48])
+def test_switch_log_matches_oracle(block):
+    """Seed switching (Sec. 3.3): the ten-shift problem whose oracle switch decisions are pinned
+    against plain per-shift COCG (two switches, each to a clear largest residual).  The GPU
+    switches after the same iterations to the same shifts, with the per-iteration update and
+    with 48-iteration blocks (where a converged seed pauses until its block ends)."""
+    S = _S()
+    rng = np.random.default_rng(68)
+    L = 5
+    Hc = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    z = rng.uniform(-7, 7, 10) + 1j * rng.uniform(0.05, 1.5, 10)
+    first = int(np.argmax(z.imag))
+    B = np.zeros((1, Hc.n), dtype=complex)
+    B[0, 3] = 1
+    H = S.Hamiltonian.from_csr(Hc)
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, torch.from_numpy(B).cuda(), tol=1e-8, max_iter=6000,
+                                         seed_index=first, block=block, check_true=True)
+    assert rc == 0
+    ref = O.shifted_cocg(Hc, z, B[0], tol=1e-8, max_iter=6000, seed_index=first)
+    assert len(ref["switches"]) == 2
+    assert S.last_switches(1)[0] == [(it + 1, t_) for it, t_ in ref["switches"]]
+    assert np.all(np.abs(rep["iters"][0] - ref["iters"]) <= 0.06 * ref["iters"] + 2)
+    Xg = X.cpu().numpy()[0]
+    for k in range(len(z)):
+        if rep["iters"][0, k] == ref["iters"][k]:
+            assert _rel(Xg[k], ref["X"][k]) < 1e-10, k
+        else:
+            d, bound = _bound_check(Hc, z[k], B[0], Xg[k], rep["res_true"][0, k], ref["X"][k])
+            assert d <= bound, (k, d, bound)
 
 
 def test_greens_diag_config1_matches_oracle():

@@ -291,3 +291,96 @@ def test_freeze_iteration_is_rounding_sensitive():
     assert np.max(np.abs(r0["iters"] - r1["iters"])) <= 5
     for k in range(len(z)):
         assert abs(r0["X"][k][0] - r1["X"][k][inv[0]]) <= 2 * 20 * 1e-10 / z[k].imag
+
+
+def test_true_residual_equals_dense_residual():
+    """Sec. 3.4 eq. residual: the oracle's true residual ||b - (z - H) x|| / ||b|| against the
+    same norm formed from the dense matrix, for complex x, b and shifts on both sides of the
+    real axis; with b = 0 the norm is returned unscaled.  Every residual-bound parity check
+    uses this routine, so an error in it (a sign of z, a dropped diagonal, a missing square
+    root or scale) would loosen those checks; each such mistake fails here."""
+    rng = np.random.default_rng(41)
+    H = random_sparse_symmetric(40, 0.1, rng, diag_scale=2.0)
+    A = H.to_dense()
+    I = np.eye(H.n)
+    for z in (0.3 + 0.05j, -1.7 + 0.4j, 2.2 - 0.3j, 0.0 + 1.0j):
+        x = rng.normal(size=H.n) + 1j * rng.normal(size=H.n)
+        b = rng.normal(size=H.n) + 1j * rng.normal(size=H.n)
+        dense = np.linalg.norm(b - (z * I - A) @ x) / np.linalg.norm(b)
+        assert abs(O.true_residual(H, z, x, b) - dense) <= 1e-13 * dense
+        # at the dense solution the residual vanishes to rounding
+        xs = np.linalg.solve(z * I - A, b)
+        assert O.true_residual(H, z, xs, b) < 1e-13
+        # a zero right-hand side: the unscaled norm of (z - H) x
+        zero = np.zeros(H.n, dtype=np.complex128)
+        ref0 = np.linalg.norm((z * I - A) @ x)
+        assert abs(O.true_residual(H, z, x, zero) - ref0) <= 1e-13 * ref0
+    # x = 0 gives exactly 1
+    b = rng.normal(size=H.n) + 1j * rng.normal(size=H.n)
+    assert O.true_residual(H, 0.5 + 0.1j, np.zeros(H.n, dtype=np.complex128), b) == pytest.approx(1.0, abs=1e-15)
+
+
+def test_cocg_tolerance_stopped_equals_dense_solve(small):
+    """Plain COCG stopped at a tolerance (the single-pair reference of the full-size checks):
+    the dense residual of its answer is at the tolerance, its recursive residual agrees with
+    the dense one, and the answer is within the Sec. 3.4 bound of the dense solve."""
+    H, z = small
+    A = H.to_dense()
+    rng = np.random.default_rng(8)
+    b = rng.normal(size=H.n) + 1j * rng.normal(size=H.n)
+    tol = 1e-9
+    for zk in z:
+        out = O.cocg(H, zk, b, tol=tol, max_iter=5000)
+        assert out["status"] == O.OK
+        rt = np.linalg.norm(b - (zk * np.eye(H.n) - A) @ out["x"]) / np.linalg.norm(b)
+        assert rt < 10 * tol
+        assert out["res"] < tol and abs(out["res"] - rt) <= 1e-3 * tol + 1e-12
+        xd = _dense_solve(H, zk, b)
+        assert np.linalg.norm(out["x"] - xd) <= rt * np.linalg.norm(b) / zk.imag * (1 + 1e-9)
+
+
+def test_switch_log_follows_residual_rule():
+    """Sec. 3.3 seed switching, as read here: when the seed's residual falls below the
+    tolerance the iteration continues from the still-active shift with the largest residual.
+    Checked against plain per-shift COCG (shift invariance makes the shifted iterates equal
+    to it in exact arithmetic): at each logged switch the old seed's own COCG has just crossed
+    the tolerance (within the few iterations rounding moves a crossing, 6 % + 2), and the new seed is
+    the unconverged shift with the largest residual, by a clear margin."""
+    rng = np.random.default_rng(68)
+    L = 5
+    H = simple_cubic(L, rng.uniform(-1, 1, L ** 3))
+    A = H.to_dense()
+    # ten shifts spread over the band with uneven damping: residual orders cross, so the seed
+    # switches twice (after 24 and 55 iterations), each time to a clear largest residual
+    z = rng.uniform(-7, 7, 10) + 1j * rng.uniform(0.05, 1.5, 10)
+    first = int(np.argmax(z.imag))
+    b = O.unit(H.n, 3)
+    tol = 1e-8
+    out = O.shifted_cocg(H, z, b, tol=tol, max_iter=6000, seed_index=first)
+    assert out["ret"] == O.OK and len(out["switches"]) == 2
+    n_max = int(out["iters"].max())
+    hist = np.zeros((len(z), n_max + 1))
+    for k in range(len(z)):
+        for m in range(1, n_max + 1):
+            out_k = O.cocg(H, z[k], b, fixed_iter=m)
+            hist[k, m] = out_k["res"]
+        # the recursive residual the stopping rule reads agrees with the dense one at the end
+        rt = np.linalg.norm(b - (z[k] * np.eye(H.n) - A) @ out_k["x"]) / np.linalg.norm(b)
+        assert abs(rt - hist[k, n_max]) <= 1e-3 * max(rt, tol) + 1e-12
+    hist[:, 0] = 1.0
+    cross = np.array([int(np.argmax(hist[k] < tol)) if np.any(hist[k] < tol) else n_max + 1 for k in range(len(z))])
+    seed = first
+    for it, t in out["switches"]:
+        n_done = it + 1
+        # near the tolerance COCG's residual is irregular, so a rounding-level difference moves
+        # a crossing by a few iterations (the same allowance as the GPU comparisons)
+        slack = 0.06 * n_done + 2
+        assert abs(cross[seed] - n_done) <= slack, (seed, cross[seed], n_done)
+        active = [k for k in range(len(z)) if k != seed and cross[k] > n_done + slack]
+        assert t in active
+        others = [hist[k, n_done] for k in active if k != t]
+        assert hist[t, n_done] > 1.5 * max(others), (t, hist[t, n_done], max(others))
+        seed = t
+    assert out["final_seed"] == seed
+    # every shift's freeze iteration is its own crossing, up to the same allowance
+    assert np.all(np.abs(out["iters"] - cross) <= 0.06 * cross + 2)
