@@ -163,6 +163,28 @@ int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, 
                 const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream);
 
 /*
+ * greens_diag for callers that cannot allocate device memory: code that runs under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels and
+ * results (bit for bit) as greens_diag without a tape; every work buffer of the solve lives in
+ * one device array of SCOCG_NOALLOC_MAX_BYTES that the library holds on each device it runs on
+ * until the process ends.  The call allocates no device or pinned memory and creates no
+ * streams, events or graphs (it runs the serial schedule with direct launches on `stream`, and
+ * its host bookkeeping is a few scalars); inputs and outputs are the caller's as in greens_diag.
+ *   Needs: o->keep_tape = 0, o->refine = 0, o->check_true = 0, o->window = 0 (EINVAL otherwise).
+ *   Scratch: about 16 n n_rhs (2 block + 4) + n_shift n_rhs (esz n + 4 esz block + 124) bytes, esz =
+ *   16 (FP64) or 8 (FP32) and block the iterations per deferred update (48 by default); a call
+ *   needing more than SCOCG_NOALLOC_MAX_BYTES returns SCOCG_EINVAL with the size it needs in
+ *   scocg_last_error(), before any work.
+ *   The array keeps the last call's contents; each call initialises what it reads.  Calls on one
+ *   device share its array, so they are serialised by a lock in the library: a second call on the
+ *   same device (another host thread) waits until the first has finished.
+ * Synchronous on stream.  Errors as greens_diag.
+ */
+#define SCOCG_NOALLOC_MAX_BYTES (128ull << 20)
+int greens_diag_noalloc(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, const int64_t *rhs_idx,
+                        const scocg_opts *o, double *G, scocg_pair_report *rep, void *stream);
+
+/*
  * Krylov-subspace diagonalization (Sec. 3.2, eq. Ham_in_KS) of the local Green's function,
  * the paper's first method and the one it compares shifted COCG against: for each unit
  * vector |j>, j = rhs_idx[c], nu steps of the three-term (Lanczos) recurrence build an

@@ -5,7 +5,7 @@ declared in include/scocg.h); this package is its Python binding, with
 PyTorch used for device memory, streams and autograd.
 """
 
-from .api import (Hamiltonian, Tape, backward, contour, csr_validate, density_matrix_energy, greens_diag,
+from .api import (Hamiltonian, Tape, backward, contour, csr_validate, density_matrix_energy, greens_diag, greens_diag_noalloc,
                   greens_diag_batched, greens_diag_waves, greens_proj, ground_state, hubbard_fermion_op,
                   krylov_greens_diag, krylov_greens_vec, last_switches, last_timing, options, set_profiling, shifted_cocg_solve)
 
@@ -18,6 +18,7 @@ __all__ = [
     "density_matrix_energy",
     "greens_diag",
     "greens_diag_batched",
+    "greens_diag_noalloc",
     "greens_diag_waves",
     "greens_proj",
     "ground_state",

@@ -68,6 +68,7 @@ EXPORTED = [
     "csr_free",
     "shifted_cocg_solve",
     "greens_diag",
+    "greens_diag_noalloc",
     "greens_diag_batched",
     "greens_proj",
     "krylov_greens_diag",
@@ -127,6 +128,8 @@ def load():
     lib.shifted_cocg_solve.restype = i32
     lib.greens_diag.argtypes = [P, i64, P, i64, P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(P), P]
     lib.greens_diag.restype = i32
+    lib.greens_diag_noalloc.argtypes = [P, i64, P, i64, P, ctypes.POINTER(Opts), P, P, P]
+    lib.greens_diag_noalloc.restype = i32
     lib.greens_diag_batched.argtypes = [i64, P, P, P, i64, P, ctypes.POINTER(Opts), P, P, P]
     lib.greens_diag_batched.restype = i32
     lib.greens_proj.argtypes = [P, i64, P, i64, P, P, ctypes.POINTER(Opts), P, P, P]

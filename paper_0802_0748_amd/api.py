@@ -240,6 +240,27 @@ def greens_diag(H: Hamiltonian, z, rhs_idx, allow_noconv=True, allow_breakdown=F
     return G, _report(rep, K, M), t, rc
 
 
+def greens_diag_noalloc(H: Hamiltonian, z, rhs_idx, G: torch.Tensor = None, allow_noconv=True, allow_breakdown=False,
+                        **opts):
+    """greens_diag whose work buffers live in the library's fixed device array (no device
+    allocation inside the call).  G, if given, is the [n_shift, n_rhs] complex128 output (allocate
+    it beforehand to keep the whole call allocation-free).  Returns (G, report, rc)."""
+    _require_gpu()
+    lib = C.load()
+    zh, zp = _z_host(z)
+    idx = np.ascontiguousarray(rhs_idx, dtype=np.int64)
+    K, M = len(idx), len(zh)
+    if G is None:
+        G = torch.empty((M, K), dtype=torch.complex128, device="cuda")
+    _check_dev(G, torch.complex128, M * K, "G")
+    o = options(**opts)
+    rep = (C.PairReport * (K * M))()
+    rc = lib.greens_diag_noalloc(H.handle, M, zp, K, idx.ctypes.data, ctypes.byref(o), G.data_ptr(), rep,
+                                 _stream_ptr())
+    C.check(rc, allow=_allowed(allow_noconv, allow_breakdown))
+    return G, _report(rep, K, M), rc
+
+
 def krylov_greens_diag(H: Hamiltonian, z, rhs_idx, nu: int, device=None):
     """Local Green's functions G_jj(z_k) by Krylov-subspace diagonalization (nu steps of the
     three-term recurrence from each unit vector e_j, then the reduced tridiagonal Hamiltonian).

@@ -4,9 +4,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1534,6 +1536,279 @@ extern "C" int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int6
         }
     }
     return rc;
+}
+
+// ------------------------------------------------------------------------------------------
+// greens_diag without device allocation
+// ------------------------------------------------------------------------------------------
+// Every buffer of the solve is carved out of one file-scope device array.  In host code the
+// array's name stands for a host-side shadow, not the device memory: its device address is
+// looked up once per device (hipGetSymbolAddress, with that device current) and only that
+// address is handed to kernels.  The array keeps its contents between calls; everything a solve
+// reads is initialised by the solve itself.
+static __device__ __align__(256) unsigned char scratch[SCOCG_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];     // serialises calls on one device (they share its array)
+void *g_scratch_ptr[kMaxDevices] = {};    // device address of the array, per device
+
+// Carves aligned sub-buffers from a base address (base = null only sizes the layout).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    void *take(size_t bytes)
+    {
+        off = (off + 255) / 256 * 256;
+        void *p = base ? (void *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+}  // namespace
+
+extern "C" int greens_diag_noalloc(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs,
+                                   const int64_t *rhs_idx, const scocg_opts *o, double *G, scocg_pair_report *rep,
+                                   void *stream)
+{
+    static_assert(sizeof(PairReportDev) == sizeof(scocg_pair_report), "report layouts differ");
+    g_err.clear();
+    g_swlog.K = 0;
+    if (!H || !z || !rhs_idx || !o || !G) return fail(SCOCG_EINVAL, "null argument");
+    REQUIRE_DEVICE((const void *)G);
+    const int64_t K = n_rhs, M = n_shift;
+    const DevCSR &d = H->d;
+    const int64_t n = d.n;
+    if (M <= 0 || K <= 0) return fail(SCOCG_EINVAL, "n_shift and n_rhs must be positive");
+    if (M > (1 << 20) || K > 65535) return fail(SCOCG_EINVAL, "too many shifts or right-hand sides");
+    for (int64_t j = 0; j < K; ++j)
+        if (rhs_idx[j] < 0 || rhs_idx[j] >= n) return fail(SCOCG_EINVAL, "rhs_idx out of range");
+    for (int64_t k = 0; k < 2 * M; ++k)
+        if (!std::isfinite(z[k])) return fail(SCOCG_EINVAL, "non-finite shift");
+    if (o->keep_tape || o->refine > 0 || o->check_true || o->window != 0)
+        return fail(SCOCG_EINVAL, "greens_diag_noalloc keeps no tape, does not refine or check true residuals, "
+                                  "and stores every shift's direction (window 0)");
+    if (!(o->tol > 0) && o->fixed_iter <= 0) return fail(SCOCG_EINVAL, "tol must be positive");
+    if (o->max_iter <= 0 && o->fixed_iter <= 0) return fail(SCOCG_EINVAL, "max_iter must be positive");
+    if (o->precision != 0 && o->precision != 1) return fail(SCOCG_EINVAL, "precision must be 0 or 1");
+    if (o->shifts_per_wg > 64) return fail(SCOCG_EINVAL, "shifts_per_wg must be at most 64");
+    if (o->schedule < 0 || o->schedule > 2) return fail(SCOCG_EINVAL, "schedule must be 0, 1 or 2");
+    const int TB = o->block > 0 ? o->block : 48;
+    if (TB != 1 && TB != 2 && TB != 4 && TB != 8 && TB != 16 && TB != 24 && TB != 32 && TB != 40 && TB != 48)
+        return fail(SCOCG_EINVAL, "block must be 1, 2, 4, 8, 16, 24, 32, 40 or 48");
+    int32_t seed = 0;
+    if (o->seed_index >= 0) {
+        if (o->seed_index >= M) return fail(SCOCG_EINVAL, "seed_index out of range");
+        seed = o->seed_index;
+    } else {
+        seed = default_seed(z, M, d.trace / (double)n);
+    }
+    const bool fixed = o->fixed_iter > 0;
+    const int32_t limit = fixed ? o->fixed_iter : o->max_iter;
+    const size_t KM = (size_t)K * M;
+    const size_t ntot = (size_t)K * n;
+    const size_t esz = o->precision == 0 ? sizeof(double2) : sizeof(float2);
+    const int R = 2 * TB + 1;
+    const int64_t nblk = (n + 255) / 256;
+
+    // the layout, in the order the buffers are carved (sized first with a null base)
+    struct Layout {
+        double2 *z, *ring, *p, *q, *Xproj, *pi, *pip, *bk, *ah, *bh, *p2;
+        void *P, *coef;
+        SeedState *seed;
+        RhsDesc *desc;
+        int64_t *prow, *idx;
+        double *res, *rn, *p1;
+        int32_t *iters, *pst, *act, *nact, *blk, *sd, *swlog, *flag, *worst;
+        uint32_t *cnt;
+        unsigned long long *stats;
+        long long *totals;
+        PairReportDev *rep;
+        size_t coef_bytes;
+    };
+    auto carve = [&](char *base, Layout &L) -> size_t {
+        Carver c{base};
+        L.z = (double2 *)c.take(M * sizeof(double2));
+        L.seed = (SeedState *)c.take(K * sizeof(SeedState));
+        L.ring = (double2 *)c.take((size_t)R * ntot * sizeof(double2));
+        L.p = (double2 *)c.take(2 * ntot * sizeof(double2));
+        L.q = (double2 *)c.take(ntot * sizeof(double2));
+        L.P = c.take((size_t)M * ntot * esz);
+        L.desc = (RhsDesc *)c.take(K * sizeof(RhsDesc));
+        L.Xproj = (double2 *)c.take(KM * sizeof(double2));
+        L.prow = (int64_t *)c.take(K * sizeof(int64_t));
+        L.idx = (int64_t *)c.take(K * sizeof(int64_t));
+        L.pi = (double2 *)c.take(KM * sizeof(double2));
+        L.pip = (double2 *)c.take(KM * sizeof(double2));
+        L.bk = (double2 *)c.take(KM * sizeof(double2));
+        L.res = (double *)c.take(KM * sizeof(double));
+        L.iters = (int32_t *)c.take(KM * sizeof(int32_t));
+        L.pst = (int32_t *)c.take(KM * sizeof(int32_t));
+        L.act = (int32_t *)c.take(KM * sizeof(int32_t));
+        L.nact = (int32_t *)c.take(2 * KM * sizeof(int32_t));
+        L.blk = (int32_t *)c.take(2 * (size_t)K * 4 * sizeof(int32_t));
+        L.ah = (double2 *)c.take((size_t)K * TB * sizeof(double2));
+        L.bh = (double2 *)c.take((size_t)K * TB * sizeof(double2));
+        L.rn = (double *)c.take((size_t)K * TB * sizeof(double));
+        L.coef_bytes = KM * TB * 2 * (o->precision == 0 ? sizeof(double2) : sizeof(float2));
+        L.coef = c.take(2 * L.coef_bytes);
+        L.p2 = (double2 *)c.take((size_t)K * nblk * sizeof(double2));
+        L.p1 = (double *)c.take((size_t)K * nblk * sizeof(double));
+        L.cnt = (uint32_t *)c.take(K * sizeof(uint32_t));
+        L.sd = (int32_t *)c.take(K * sizeof(int32_t));
+        L.stats = (unsigned long long *)c.take(3 * sizeof(unsigned long long));
+        L.swlog = (int32_t *)c.take(KM * 2 * sizeof(int32_t));
+        L.flag = (int32_t *)c.take(sizeof(int32_t));
+        L.worst = (int32_t *)c.take(sizeof(int32_t));
+        L.totals = (long long *)c.take(2 * sizeof(long long));
+        L.rep = (PairReportDev *)c.take(KM * sizeof(PairReportDev));
+        return c.off;
+    };
+    Layout L{};
+    const size_t need = carve(nullptr, L);
+    if (need > (size_t)SCOCG_NOALLOC_MAX_BYTES)
+        return fail(SCOCG_EINVAL, "greens_diag_noalloc needs " + std::to_string(need) + " bytes of scratch, more than "
+                                  "its fixed " + std::to_string((size_t)SCOCG_NOALLOC_MAX_BYTES) +
+                                  " (fewer right-hand sides or shifts, or a shorter block, reduce it)");
+
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SCOCG_EINVAL, "device index beyond the supported range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(SCOCG_EHIP, "scratch array has no device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    carve((char *)g_scratch_ptr[dev], L);
+    hipStream_t st = (hipStream_t)stream;
+    const auto t_start = std::chrono::steady_clock::now();
+    g_timing = scocg_timing{};
+
+    SolveDev s{};
+    s.ntot = (int64_t)ntot;
+    s.n = n;
+    s.K = K;
+    s.M = M;
+    s.TB = TB;
+    s.R = R;
+    s.precision = o->precision;
+    s.fixed = fixed ? 1 : 0;
+    s.switching = o->seed_switching ? 1 : 0;
+    s.tol = o->tol;
+    s.nblk = nblk;
+    s.shifts_per_wg = o->shifts_per_wg > 0 ? o->shifts_per_wg : (int)std::min<int64_t>(M, TB >= 24 ? 64 : 32);
+    s.zper = 0;
+    s.spmv_rb = K >= 2 ? 2 : 1;
+    (d.d_hub ? s.has_hub : s.has_sell) = 1;
+    (n >= RED_BIG_ROWS ? s.has_red_big : s.has_red_small) = 1;
+    s.hub_lds = 1;
+    if (d.d_hub) {
+        if (d.hub_Dd > HUB_LDS_MAX || n / d.hub_Dd > (n + 255) / 256) s.hub_lds = 0;
+        s.hub_du_max = n / d.hub_Dd;
+    }
+    s.z = L.z;
+    s.seed = L.seed;
+    s.ring = L.ring;
+    s.p = L.p;
+    s.q = L.q;
+    s.X = nullptr;
+    s.P = L.P;
+    s.Mst = M;
+    s.wshift = nullptr;
+    s.wslot = nullptr;
+    s.Uproj = nullptr;
+    s.Xproj = L.Xproj;
+    s.wproj = nullptr;
+    s.shist = nullptr;
+    s.part3 = nullptr;
+    s.proj_row = L.prow;
+    s.pi = L.pi;
+    s.pi_prev = L.pip;
+    s.beta_k = L.bk;
+    s.res = L.res;
+    s.iters = L.iters;
+    s.pstatus = L.pst;
+    s.active = L.act;
+    s.nact = L.nact;
+    s.ahist = L.ah;
+    s.bhist = L.bh;
+    s.rnhist = L.rn;
+    s.coef = L.coef;
+    s.blk = L.blk;
+    s.part2 = L.p2;
+    s.part1 = L.p1;
+    s.cnt = L.cnt;
+    s.stats = L.stats;
+    s.swlog = L.swlog;
+    s.desc = L.desc;
+
+    const RhsDesc proto{d.d_slice_ptr, d.d_slice_w, d.d_ell_col, d.d_ell_val, d.nslices, n, 0, d.d_hub};
+    HIPCHK(launch_fill_desc(proto, K, seed, L.desc, L.sd, st));
+    HIPCHK(hipMemcpyAsync(L.z, z, M * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(L.idx, rhs_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(L.prow, rhs_idx, K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // counters, activity counts, block records, statistics and the report sums start at zero
+    HIPCHK(launch_zero(L.cnt, K * sizeof(uint32_t), st));
+    HIPCHK(launch_zero(L.nact, 2 * KM * sizeof(int32_t), st));
+    HIPCHK(launch_zero(L.blk, 2 * (size_t)K * 4 * sizeof(int32_t), st));
+    HIPCHK(launch_zero(L.stats, 3 * sizeof(unsigned long long), st));
+    HIPCHK(launch_zero(L.swlog, KM * 2 * sizeof(int32_t), st));
+    HIPCHK(launch_zero(L.worst, sizeof(int32_t), st));
+    HIPCHK(launch_zero(L.totals, 2 * sizeof(long long), st));
+    HIPCHK(launch_zero(s.p, 2 * ntot * sizeof(double2), st));
+    HIPCHK(launch_init(s, nullptr, L.idx, L.sd, limit, st));
+
+    // the block loop of solve() in its serial schedule, launched directly (no streams, events
+    // or graphs are created); the stop test reads one flag computed on the device
+    SolveDev sp[2] = {s, s};
+    for (int q = 0; q < 2; ++q) {
+        sp[q].coef = (char *)L.coef + q * L.coef_bytes;
+        sp[q].nact = L.nact + q * KM;
+        sp[q].blk = L.blk + q * (size_t)K * 4;
+    }
+    const int per_sync = std::max(1, 64 / TB);
+    const int64_t max_blocks = (int64_t)K * ((int64_t)limit + 4 * M + 8) + 8 + per_sync;
+    int64_t blocks = 0;
+    for (;;) {
+        for (int b = 0; b < per_sync; ++b) {
+            const int par = (int)(blocks & 1);
+            HIPCHK(launch_switch_vectors(sp[par], st));
+            for (int t = 0; t < TB; ++t) HIPCHK(launch_seed_iteration(sp[par], st));
+            HIPCHK(launch_pair_scalars(sp[par], st));
+            HIPCHK(launch_flush(sp[par], st));
+            HIPCHK(launch_block_finalize(sp[par], st));
+            ++blocks;
+        }
+        int32_t stopped = 0;
+        HIPCHK(launch_all_stopped(L.seed, K, L.flag, st));
+        HIPCHK(hipMemcpyAsync(&stopped, L.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (stopped) break;
+        if (blocks > max_blocks) return fail(SCOCG_EHIP, "iteration driver did not terminate");
+    }
+    HIPCHK(launch_gather_diag(s, L.idx, (double2 *)G, st));
+    HIPCHK(launch_pack_report(K, M, s.fixed, L.iters, L.pst, L.res, L.seed, L.rep, L.worst, L.totals, st));
+    int32_t worst = 0;
+    long long totals[2] = {0, 0};
+    unsigned long long stats[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(&worst, L.worst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(totals, L.totals, sizeof(totals), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(stats, L.stats, sizeof(stats), hipMemcpyDeviceToHost, st));
+    if (rep) HIPCHK(hipMemcpyAsync(rep, L.rep, KM * sizeof(scocg_pair_report), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    g_timing.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    g_timing.iterations = totals[0];
+    g_timing.switches = totals[1];
+    g_timing.blocks = blocks;
+    g_timing.update_bytes = (double)stats[0];
+    g_timing.update_flops = (double)stats[2];
+    if (worst == 2) return fail(SCOCG_EBREAKDOWN, "COCG breakdown on at least one pair");
+    if (worst == 1) return fail(SCOCG_ENOCONV, "at least one pair did not converge");
+    return SCOCG_OK;
 }
 
 // <w_j|(z_k - H)^{-1}|b_j> for dense right-hand sides b_j and projection vectors w_j (Sec. 3.3:

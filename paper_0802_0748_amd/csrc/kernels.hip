@@ -1316,6 +1316,91 @@ __global__ void k_pair_weights_conj(int64_t K, int64_t M, const double2 *__restr
 }
 
 // ---------------------------------------------------------------------------------------
+// set-up and reports computed on the device (used by the entry point that allocates nothing,
+// so that no per-rhs or per-pair table has to be built on the host)
+// ---------------------------------------------------------------------------------------
+// desc[j] = proto with its vectors at j * proto.n; seeds[j] = seed; idx[j] copied as given
+__global__ void k_fill_desc(RhsDesc proto, int64_t K, int32_t seed, RhsDesc *__restrict__ desc,
+                            int32_t *__restrict__ seeds)
+{
+    const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (j >= K) return;
+    RhsDesc d = proto;
+    d.voff = j * proto.n;
+    desc[j] = d;
+    seeds[j] = seed;
+}
+
+// flag[0] = 1 when every right-hand side has stopped
+__global__ void k_all_stopped(const SeedState *__restrict__ seed, int64_t K, int32_t *__restrict__ flag)
+{
+    __shared__ int sh[WG];
+    int run = 0;
+    for (int64_t j = threadIdx.x; j < K; j += WG) run |= seed[j].status != SEED_STOPPED ? 1 : 0;
+    sh[threadIdx.x] = run;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] |= sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flag[0] = sh[0] ? 0 : 1;
+}
+
+// Per-pair reports in the C ABI's layout, the worst status (2 breakdown, 1 not converged) and,
+// from the first workgroup, the seed iterations and switches summed over right-hand sides.
+// worst and totals start at zero.
+__global__ void k_pack_report(int64_t K, int64_t M, int fixed, const int32_t *__restrict__ iters,
+                              const int32_t *__restrict__ pstatus, const double *__restrict__ res,
+                              const SeedState *__restrict__ seed, PairReportDev *__restrict__ rep,
+                              int32_t *__restrict__ worst, long long *__restrict__ totals)
+{
+    const int64_t pair = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (pair < K * M) {
+        const int32_t stv = pstatus[pair];
+        PairReportDev r;
+        r.iters = iters[pair];
+        r.status = (fixed && stv == PAIR_NOCONV) ? PAIR_OK : stv;
+        r.res = res[pair];
+        r.res_true = -1.0;
+        rep[pair] = r;
+        const int code = stv == PAIR_BREAKDOWN ? 2 : ((stv == PAIR_NOCONV && !fixed) ? 1 : 0);
+        if (code) atomicMax(worst, code);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        long long it = 0, sw = 0;
+        for (int64_t j = 0; j < K; ++j) {
+            it += seed[j].iter;
+            sw += seed[j].switches;
+        }
+        totals[0] = it;
+        totals[1] = sw;
+    }
+}
+
+hipError_t launch_fill_desc(const RhsDesc &proto, int64_t K, int32_t seed, RhsDesc *desc, int32_t *seeds,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_desc, dim3((unsigned)((K + WG - 1) / WG)), dim3(WG), 0, st, proto, K, seed, desc, seeds);
+    return hipGetLastError();
+}
+
+hipError_t launch_all_stopped(const SeedState *seed, int64_t K, int32_t *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_all_stopped, dim3(1), dim3(WG), 0, st, seed, K, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_report(int64_t K, int64_t M, int fixed, const int32_t *iters, const int32_t *pstatus,
+                              const double *res, const SeedState *seed, PairReportDev *rep, int32_t *worst,
+                              long long *totals, hipStream_t st)
+{
+    const int64_t KM = K * M;
+    hipLaunchKernelGGL(k_pack_report, dim3((unsigned)((KM + WG - 1) / WG)), dim3(WG), 0, st, K, M, fixed, iters,
+                       pstatus, res, seed, rep, worst, totals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------------------
 static inline dim3 grid2(int64_t x, int64_t y) { return dim3((unsigned)x, (unsigned)y, 1); }

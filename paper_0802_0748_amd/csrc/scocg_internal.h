@@ -183,6 +183,19 @@ struct SolveDev {
                                // a shift becomes the seed at most once, so M entries suffice
 };
 
+// A pair report with the layout of the C ABI's scocg_pair_report.
+struct PairReportDev {
+    int32_t iters, status;
+    double res, res_true;
+};
+
+hipError_t launch_fill_desc(const RhsDesc &proto, int64_t K, int32_t seed, RhsDesc *desc, int32_t *seeds,
+                            hipStream_t st);
+hipError_t launch_all_stopped(const SeedState *seed, int64_t K, int32_t *flag, hipStream_t st);
+hipError_t launch_pack_report(int64_t K, int64_t M, int fixed, const int32_t *iters, const int32_t *pstatus,
+                              const double *res, const SeedState *seed, PairReportDev *rep, int32_t *worst,
+                              long long *totals, hipStream_t st);
+
 hipError_t launch_init(const SolveDev &s, const double2 *B, const int64_t *unit_idx,
                        const int32_t *seed_idx, int32_t limit, hipStream_t st);
 // one seed iteration (four launches, see kernels.hip)
