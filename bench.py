@@ -50,6 +50,8 @@ def parse():
                     help="default fp64 (fp32 storage for the batch workload)")
     ap.add_argument("--problems", type=int, default=8, help="lattices in the batch workload")
     ap.add_argument("--wave", type=int, default=8, help="lattices per batched solve in the batch workload")
+    ap.add_argument("--update-form", default="auto", choices=["auto", "step", "expanded"],
+                    help="deferred update: step form, or expanded (FP64 matrix cores); auto is the step form")
     ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "overlap"],
                     help="deferred update in order with the seed iterations, or overlapped with the next block")
     ap.add_argument("--matrix-free", action="store_true",
@@ -938,7 +940,7 @@ def main():
         B = torch.from_numpy(p.rhs_dense()).to(dev)
         X = torch.empty((K, M, n), dtype=torch.complex128, device=dev)
     opts = dict(tol=p.tol, max_iter=p.max_iter, precision=args.precision, block=args.block,
-                shifts_per_wg=args.shifts_per_wg, schedule=args.schedule)
+                shifts_per_wg=args.shifts_per_wg, schedule=args.schedule, update_form=args.update_form)
     if greens:
         opts["window"] = args.window
     elif args.window:

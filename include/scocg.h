@@ -76,7 +76,14 @@ typedef struct {
                                2 overlapped with the next block's iterations on a second stream; 0 automatic
                                (overlapped when the stored directions hold at least 2^24 complex numbers, where
                                the update outweighs the cost of the cross-stream waits).  Same bits either way. */
-    int32_t reserved[2];
+    int32_t update_form;    /* deferred update of x_k, u_k: 1 the step form (two complex multiply-adds per step,
+                               the same bits for every block length); 2 the expanded form, in which a block
+                               becomes x += gamma u + sum_s c_s r_s and u = delta u + sum_s d_s r_s with the
+                               per-pair weights c_s, d_s (a contraction with the residual history on FP64 matrix
+                               cores; FP64 storage, full solutions, blocks of 24 or more, EINVAL otherwise);
+                               0 automatic (the step form, the faster one on gfx950).  Both forms agree to
+                               rounding. */
+    int32_t reserved;
 } scocg_opts;
 
 typedef struct {

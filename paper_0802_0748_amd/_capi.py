@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
         ("refine", ctypes.c_int32),
         ("window", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("update_form", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -36,7 +36,7 @@ def _check_dev(t: torch.Tensor, dtype, numel, name):
 
 def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switching=True, fixed_iter=0, block=0,
             shifts_per_wg=0, check_true=False, keep_tape=False, no_graph=False, refine=0, window=0,
-            schedule="auto") -> C.Opts:
+            schedule="auto", update_form="auto") -> C.Opts:
     o = C.Opts()
     C.load().scocg_default_opts(ctypes.byref(o))
     o.tol = float(tol)
@@ -53,6 +53,7 @@ def options(tol=1e-8, max_iter=3000, precision="fp64", seed_index=-1, seed_switc
     o.refine = int(refine)
     o.window = int(window)
     o.schedule = {"auto": 0, "serial": 1, "overlap": 2, 0: 0, 1: 1, 2: 2}[schedule]
+    o.update_form = {"auto": 0, "step": 1, "expanded": 2, 0: 0, 1: 1, 2: 2}[update_form]
     return o
 
 

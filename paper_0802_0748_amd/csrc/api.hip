@@ -720,6 +720,18 @@ int solve(SolveRequest &rq, hipStream_t st)
     ALLOC(brn, K * TB * sizeof(double));
     const size_t coef_bytes = KM * TB * 2 * (o.precision == 0 ? sizeof(double2) : sizeof(float2));
     ALLOC(bcoef, 2 * coef_bytes);
+    // the expanded update form (FP64 matrix cores) for FP64 full solutions in blocks of 24 and more
+    if (o.update_form < 0 || o.update_form > 2) return fail(SCOCG_EINVAL, "update_form must be 0, 1 or 2");
+    const bool can_expand = o.precision == 0 && need_full && Mst == M && TB >= 24;
+    if (o.update_form == 2 && !can_expand)
+        return fail(SCOCG_EINVAL, "the expanded update form needs FP64 storage, full solutions and blocks of 24 or more");
+    // automatic: the step form, which is faster on gfx950 (the FP64 matrix cores have the vector
+    // units' peak, and the expanded form's per-lane weight loads and 16-pair granularity cost more
+    // than the step form's latency; measured 22.3 against 14.0 ms per diamond launch alone)
+    s.expanded = (o.update_form == 2) ? 1 : 0;
+    const size_t coefx_bytes = s.expanded ? KM * (size_t)(6 * TB + 4) * sizeof(double) : 0;
+    DevBuf bcoefx;
+    if (s.expanded) ALLOC(bcoefx, 2 * coefx_bytes);
     ALLOC(bp2, K * s.nblk * sizeof(double2));
     ALLOC(bp1, K * s.nblk * sizeof(double));
     ALLOC(bcnt, K * sizeof(uint32_t));
@@ -844,6 +856,7 @@ int solve(SolveRequest &rq, hipStream_t st)
     SolveDev sp[2] = {s, s};
     for (int q = 0; q < 2; ++q) {
         sp[q].coef = (char *)bcoef.ptr + q * coef_bytes;
+        sp[q].coefx = s.expanded ? (double *)((char *)bcoefx.ptr + q * coefx_bytes) : nullptr;
         sp[q].nact = bnact.as<int32_t>() + q * KM;
         sp[q].blk = bblk.as<int32_t>() + q * (size_t)K * 4;
     }

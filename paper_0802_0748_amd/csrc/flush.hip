@@ -349,6 +349,130 @@ __global__ void __launch_bounds__(64 * FL_W)
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Expanded form on the FP64 matrix cores (full solutions, FP64 storage).  Per pair the block is
+//   x_out = x_in + gamma u_in + sum_s c_s r_s,   u_out = delta u_in + sum_s d_s r_s
+// with the weights c_s, d_s of k_pair_scalars: for a 64-row tile and a group of up to 64 shifts
+// of one rhs that is the complex product [pairs x T] . [T x 64 rows] of the weights with the
+// residual history, formed with v_mfma_f64_16x16x4f64 and Gauss's three real products
+// (Re = C_r R_r - C_i R_i, Im = (C_r + C_i)(R_r + R_i) - C_r R_r - C_i R_i), so 12 instead of
+// 16 flops per pair, row and step.  The MFMA lane layout on gfx950 (checked on the device):
+// A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i % 4), element
+// i / 4.  Here i is a pair, j a row and k a step: a lane's four results are one row of four
+// pairs, so each result row of 16 lanes is one pair's 16 consecutive rows (256 B).
+// A workgroup: eight waves, the history of its 64 rows in LDS (as in k_flush_lds); the group's
+// active shifts are compacted and wave w takes active slots 16 (w % 4) .. + 15 on rows
+// 32 (w / 4) .. + 31 (two 16-row MFMA blocks).  Frozen slots cost nothing, and a pair's result
+// depends only on its own weights and the history, not on which slot or batch it sits in.
+// ---------------------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int TB>
+__global__ void __launch_bounds__(64 * FL_W)
+    k_flush_mfma(const int32_t *__restrict__ blk, const double2 *__restrict__ ring, const double *__restrict__ coefx,
+                 const int32_t *__restrict__ nact, double2 *__restrict__ X, double2 *__restrict__ P,
+                 const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G, int ngroups, int R)
+{
+    static_assert(TB % 4 == 0 && FL_W == 8, "four steps per MFMA, eight waves");
+    constexpr int KS = TB / 4;
+    const int64_t KM = M * (int64_t)(gridDim.y / ngroups);  // pairs of the solve (weights are pair-fastest)
+    const int64_t j = blockIdx.y / ngroups;
+    const int g = blockIdx.y % ngroups;
+    const int ns = blk[4 * j + 0];
+    if (ns == 0) return;
+    const int base = blk[4 * j + 1];
+    const bool fresh = blk[4 * j + 2] != 0;
+    const int64_t n = desc[j].n;
+    const int64_t voff = desc[j].voff;
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    if (row0 >= n) return;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int lane = threadIdx.x % 64;
+    const int64_t k0 = (int64_t)g * G;
+    const int64_t k1 = min(k0 + G, M);
+    const bool act = lane < k1 - k0 && nact[j * M + k0 + lane] > 0;
+    const uint64_t mask = __ballot(act);
+    if (mask == 0) return;  // frozen group: leave before reading the history
+    const int nactive = __popcll(mask);
+    __shared__ double2 lr[TB * 64];
+    __shared__ int slot_of[64];
+    const bool valid_row = row0 + lane < n;
+    for (int t = w; t < TB; t += FL_W)
+        lr[t * 64 + lane] = (t < ns && valid_row) ? ring[(int64_t)((base + t) % R) * ntot + voff + row0 + lane]
+                                                  : cmk(0, 0);
+    if (w == 0 && act) slot_of[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
+    __syncthreads();
+    const int pg = w & 3, rh = w >> 2;
+    if (16 * pg >= nactive) return;  // no active slots for this wave
+    // A operands: lane -> active slot 16 pg + (lane % 16), step 4 kb + lane / 16
+    const int ia = 16 * pg + (lane & 15);
+    const bool va = ia < nactive;
+    const double *cp = coefx + (j * M + k0 + slot_of[va ? ia : 0]);
+    v4d acc[2][6];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[rb][q] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int kb = 0; kb < KS; ++kb) {
+        const int st = 4 * kb + (lane >> 4);
+        const double *c = cp + (int64_t)(st * 6) * KM;
+        double a[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) a[q] = va ? c[q * KM] : 0.0;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const double2 r = lr[st * 64 + rh * 32 + rb * 16 + (lane & 15)];
+            const double br = r.x, bi = r.y, bs = r.x + r.y;
+            acc[rb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], br, acc[rb][0], 0, 0, 0);
+            acc[rb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], bi, acc[rb][1], 0, 0, 0);
+            acc[rb][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], bs, acc[rb][2], 0, 0, 0);
+            acc[rb][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], br, acc[rb][3], 0, 0, 0);
+            acc[rb][4] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[4], bi, acc[rb][4], 0, 0, 0);
+            acc[rb][5] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[5], bs, acc[rb][5], 0, 0, 0);
+        }
+    }
+    X += M * voff;
+    P += M * voff;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const int64_t row = row0 + rh * 32 + rb * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * pg + (lane >> 4) + 4 * v;
+            if (row >= n || i >= nactive) continue;
+            const int64_t slot = k0 + slot_of[i];
+            const double *gd = coefx + (int64_t)(6 * TB) * KM + (j * M + slot);
+            double2 x = cmk(0, 0), u = cmk(0, 0);
+            if (!fresh) {
+                x = ld_nt(X + slot * n + row);
+                u = ld_nt(P + slot * n + row);
+            }
+            const double t1 = acc[rb][0][v], t2 = acc[rb][1][v], t3 = acc[rb][2][v];
+            const double e1 = acc[rb][3][v], e2 = acc[rb][4][v], e3 = acc[rb][5][v];
+            const double2 gu = cmul(make_double2(gd[0], gd[KM]), u), du = cmul(make_double2(gd[2 * KM], gd[3 * KM]), u);
+            const double2 xo = make_double2(x.x + gu.x + (t1 - t2), x.y + gu.y + (t3 - t1 - t2));
+            const double2 uo = make_double2(du.x + (e1 - e2), du.y + (e3 - e1 - e2));
+            st_nt(X + slot * n + row, xo);
+            st_nt(P + slot * n + row, uo);
+        }
+    }
+}
+
+template <int TB>
+static hipError_t flush_mfma(const SolveDev &s, hipStream_t st)
+{
+    const int G = s.shifts_per_wg;
+    if (G < 1 || G > 64 || s.precision != 0 || !s.X || s.Xproj || s.wshift || s.Mst != s.M)
+        return hipErrorInvalidConfiguration;
+    const int ng = (int)((s.M + G - 1) / G);
+    if (s.K * ng > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const dim3 g((unsigned)(s.nblk * (WG / 64)), (unsigned)(s.K * ng));
+    hipLaunchKernelGGL((k_flush_mfma<TB>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, (const double *)s.coefx, s.nact,
+                       (double2 *)s.X, (double2 *)s.P, s.desc, s.ntot, s.M, G, ng, s.R);
+    return hipGetLastError();
+}
+
 template <int TB, int C, int NPW, typename V>
 static hipError_t flush_lds(const SolveDev &s, hipStream_t st)
 {
@@ -405,6 +529,15 @@ static hipError_t flush_tb(const SolveDev &s, hipStream_t st)
 
 hipError_t launch_flush(const SolveDev &s, hipStream_t st)
 {
+    if (s.expanded) {
+        switch (s.TB) {
+        case 24: return flush_mfma<24>(s, st);
+        case 32: return flush_mfma<32>(s, st);
+        case 40: return flush_mfma<40>(s, st);
+        case 48: return flush_mfma<48>(s, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (s.TB) {
     case 1: return flush_tb<1>(s, st);
     case 2: return flush_tb<2>(s, st);

@@ -848,6 +848,40 @@ __device__ inline unsigned long long pair_scalars_one(const SolveDev &s, int64_t
         cf[2 * t + 0] = to_v<V>(cmk(0, 0));
         cf[2 * t + 1] = to_v<V>(cmk(1, 0));
     }
+    if (sizeof(V) == sizeof(double2) && s.expanded) {
+        // The block's steps unrolled (u_in, x_in the values at the block's start):
+        //   u_out = delta u_in + sum_s d_s r_s,   x_out = x_in + gamma u_in + sum_s c_s r_s,
+        //   d_s = prod_{q=s+1}^{T-1} b'_q,  c_s = sum_{t>=s} a'_t prod_{q=s+1}^{t} b'_q,
+        // by the backward recurrences c_s = a'_s + b'_{s+1} c_{s+1}, d_s = b'_{s+1} d_{s+1}
+        // (c_{T-1} = a'_{T-1}, d_{T-1} = 1), gamma = b'_0 c_0, delta = b'_0 d_0.  Padded steps
+        // (a' = 0, b' = 1) give c_s = 0, d_s = 1, as the step form does.
+        // Layout [6 TB + 4][K M], pair fastest: the threads of a wave write consecutive pairs.
+        const double2 *cfd = (const double2 *)cf;
+        const int64_t KM = s.K * s.M;
+        double *cx = s.coefx + pair;
+        double2 c = cfd[2 * (s.TB - 1) + 0], d = cmk(1, 0);
+        for (int t = s.TB - 1; t >= 0; --t) {
+            if (t < s.TB - 1) {
+                const double2 bn = cfd[2 * (t + 1) + 1];
+                c = cadd(cfd[2 * t + 0], cmul(bn, c));
+                d = cmul(bn, d);
+            }
+            double *e = cx + (int64_t)(6 * t) * KM;
+            e[0 * KM] = c.x;
+            e[1 * KM] = c.y;
+            e[2 * KM] = c.x + c.y;
+            e[3 * KM] = d.x;
+            e[4 * KM] = d.y;
+            e[5 * KM] = d.x + d.y;
+        }
+        const double2 b0 = cfd[1];
+        const double2 gam = cmul(b0, c), del = cmul(b0, d);
+        double *e = cx + (int64_t)(6 * s.TB) * KM;
+        e[0 * KM] = gam.x;
+        e[1 * KM] = gam.y;
+        e[2 * KM] = del.x;
+        e[3 * KM] = del.y;
+    }
     // algorithmic bytes of this pair's deferred update: u_k (and x_k unless projected)
     // written once, and read once unless this is the first block
     const unsigned long long esz = s.precision == 0 ? 16ull : 8ull;

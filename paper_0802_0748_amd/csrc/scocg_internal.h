@@ -173,6 +173,10 @@ struct SolveDev {
     int shifts_per_wg;
     int zper;                  // 1: one shift per rhs (M = 1, z has K entries), used by refinement
     int spmv_rb;               // right-hand sides per SpMV thread (2: each rhs pair 2i, 2i+1 shares its matrix)
+    int expanded;              // 1: the deferred update uses the expanded form (weights in coefx, MFMA kernel)
+    double *coefx;             // [6 TB + 4][K*M] expanded weights of this block, pair fastest (double-buffered
+                               // like coef): per step s (Re c_s, Im c_s, Re c_s + Im c_s, Re d_s, Im d_s,
+                               // Re d_s + Im d_s), then gamma (re, im), delta (re, im)
     int has_sell, has_hub;     // some rhs has a stored matrix / a matrix-free Hubbard operator
     int hub_lds;               // every Hubbard operator's down-spin block fits the LDS-tiled product
     int has_red_small, has_red_big; // some rhs below / at or above 2^21 rows (per-rhs reduction width)

@@ -42,8 +42,8 @@ def test_waves_equal_one_batched_solve():
 def test_tuner_returns_a_candidate_and_caches_it(tmp_path):
     """The tuner times each candidate shape on the problem itself, keeps the fastest, and
     answers from its cache the second time; a solve with the tuned shape gives the same
-    bits as the default shape (block length and shifts per workgroup change only the
-    schedule of the same arithmetic)."""
+    bits as the default shape in the step form of the update (block length and shifts per
+    workgroup change only the schedule of the same arithmetic)."""
     from paper_0802_0748_amd import tune
 
     S = _S()
@@ -62,7 +62,7 @@ def test_tuner_returns_a_candidate_and_caches_it(tmp_path):
     again = tune.tune(H, z, B, iters=48, cache=cache, blocks=(8, 24), shifts_per_wg=(16, 32))
     assert again == best
     Xt, rept, _, _ = S.shifted_cocg_solve(H, z, B, tol=1e-10, max_iter=3000, block=best["block"],
-                                          shifts_per_wg=best["shifts_per_wg"])
-    Xd, repd, _, _ = S.shifted_cocg_solve(H, z, B, tol=1e-10, max_iter=3000)
+                                          shifts_per_wg=best["shifts_per_wg"], update_form="step")
+    Xd, repd, _, _ = S.shifted_cocg_solve(H, z, B, tol=1e-10, max_iter=3000, update_form="step")
     assert np.array_equal(rept["iters"], repd["iters"])
     assert np.array_equal(Xt.cpu().numpy(), Xd.cpu().numpy())

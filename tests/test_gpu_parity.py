@@ -46,10 +46,11 @@ def test_fixed_iteration_fp64_matches_oracle(n):
         assert np.all(rep["iters"][j] == iters)
 
 
-@pytest.mark.parametrize("iters", [96, 144])
-def test_fixed_iteration_long_blocks_match_oracle(iters):
+@pytest.mark.parametrize("iters,form", [(96, "step"), (144, "step"), (96, "expanded"), (144, "expanded")])
+def test_fixed_iteration_long_blocks_match_oracle(iters, form):
     """The production update (48-iteration blocks, the LDS-staged kernel with up to 64 shifts per
-    workgroup) against the oracle over two and three full blocks: 1728 rows (a ragged last
+    workgroup; and the expanded form on the matrix cores) against the oracle over two and three
+    full blocks: 1728 rows (a ragged last
     64-row tile), 70 shifts (a full group of 64 and a ragged one of 6), three dense right-hand
     sides.  The shifts lie just below the spectrum (Re z = lambda_min - 0.003 .. 0.3), where the
     shifted matrices are close to definite and COCG converges smoothly, so rounding is not
@@ -68,11 +69,11 @@ def test_fixed_iteration_long_blocks_match_oracle(iters):
     B = r2.normal(size=(3, Hc.n)) + 1j * r2.normal(size=(3, Hc.n))
     H = S.Hamiltonian.from_csr(Hc)
     Bt = torch.from_numpy(B).cuda()
-    X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, fixed_iter=iters, block=48)
+    X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, fixed_iter=iters, block=48, update_form=form)
     assert rc == 0 and np.all(rep["iters"] == iters)
     Xg = X.cpu().numpy()
     # the later blocks do change the solutions well above the comparison bar
-    X1, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=48, block=48)
+    X1, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=48, block=48, update_form=form)
     change = np.linalg.norm(Xg - X1.cpu().numpy(), axis=2) / np.linalg.norm(Xg, axis=2)
     assert np.median(change) > 1e-7
     worst = 0.0
@@ -86,14 +87,15 @@ def test_fixed_iteration_long_blocks_match_oracle(iters):
 
 
 def test_block_length_does_not_change_bits():
-    """The deferred shift update applies the same operations in the same order for any block length."""
+    """The step form of the deferred shift update applies the same operations in the same order
+    for any block length."""
     S = _S()
     Hc, z, B = _problem(300, 2)
     H = S.Hamiltonian.from_csr(Hc)
     Bt = torch.from_numpy(B).cuda()
     ref = None
     for tb in (1, 2, 4, 8, 16, 24, 32, 40, 48):
-        X, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=37, seed_index=0, block=tb)
+        X, _, _, _ = S.shifted_cocg_solve(H, z, Bt, fixed_iter=37, seed_index=0, block=tb, update_form="step")
         Xn = X.cpu().numpy()
         if ref is None:
             ref = Xn
@@ -111,7 +113,8 @@ def test_block_length_does_not_change_bits_with_freezing_and_switching(precision
     Bt = torch.from_numpy(B).cuda()
     ref = None
     for tb in (1, 8, 24, 32, 48):
-        X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision, block=tb)
+        X, rep, _, rc = S.shifted_cocg_solve(H, z, Bt, tol=1e-10, max_iter=3000, precision=precision, block=tb,
+                                             update_form="step")
         assert rc == 0
         assert S.last_timing()["switches"] > 0
         cur = (X.cpu().numpy(), rep["iters"].copy())
@@ -139,7 +142,7 @@ def test_long_block_update_many_shift_groups(precision):
     ref = None
     for tb, g in [(16, 0), (24, 0), (32, 0), (40, 37), (48, 0), (48, 37), (48, 1)]:
         X, rep, _, rc = S.shifted_cocg_solve(H, z, B, tol=1e-9, max_iter=4000, precision=precision, block=tb,
-                                             shifts_per_wg=g)
+                                             shifts_per_wg=g, update_form="step")
         assert rc == 0, (tb, g)
         cur = (X.cpu().numpy(), rep["iters"].copy())
         if ref is None:
@@ -148,6 +151,61 @@ def test_long_block_update_many_shift_groups(precision):
             assert np.array_equal(cur[1], ref[1]), (tb, g)
             assert np.array_equal(cur[0], ref[0]), (tb, g)
     assert len(np.unique(ref[1])) > 10
+
+
+def test_expanded_update_form_against_step_form():
+    """The expanded update form (blocks unrolled into per-pair weights, contracted with the
+    residual history on the FP64 matrix cores): a pair's result depends only on its own weights
+    and the history, so it is bit for bit the same for every shift-group size (64, 37, 1, which
+    move pairs to other slots, waves and workgroups) and with other pairs frozen around it; against
+    the step form it agrees to rounding (fixed iterations: 1e-12 relative); with freezing and seed
+    switching (150 shifts, 1111 rows, tol 1e-9) a freeze decision can move by rounding (after a
+    switch the new seed's direction is one of the vectors the two forms round differently), so
+    freeze iterations agree within 6 % + 2 and the solutions within the residual bound."""
+    S = _S()
+    rng = np.random.default_rng(77)
+    n, M = 1111, 150
+    Hc = random_sparse_symmetric(n, 0.01, rng, diag_scale=2.0)
+    H = S.Hamiltonian.from_csr(Hc)
+    z = np.linspace(-3, 3, M) + 1j * rng.uniform(0.02, 0.5, M)
+    B = torch.from_numpy(rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))).cuda()
+    Xs, _, _, _ = S.shifted_cocg_solve(H, z, B, fixed_iter=30, block=48, update_form="step")
+    Xe, _, _, _ = S.shifted_cocg_solve(H, z, B, fixed_iter=30, block=48, update_form="expanded")
+    Xs, Xe = Xs.cpu().numpy(), Xe.cpu().numpy()
+    rel = np.linalg.norm(Xe - Xs, axis=2) / np.linalg.norm(Xs, axis=2)
+    assert rel.max() < 1e-12, rel.max()
+    ref = None
+    for g in (0, 37, 1):
+        X, rep, _, rc = S.shifted_cocg_solve(H, z, B, tol=1e-9, max_iter=4000, block=48, shifts_per_wg=g,
+                                             update_form="expanded")
+        assert rc == 0
+        cur = (X.cpu().numpy(), rep["iters"].copy())
+        if ref is None:
+            ref = cur
+        else:
+            assert np.array_equal(cur[1], ref[1]), g
+            assert np.array_equal(cur[0], ref[0]), g
+    Bn = B.cpu().numpy()
+
+    def close(X, rep, tag):
+        assert np.all(np.abs(rep["iters"] - ref[1]) <= 0.06 * ref[1] + 2), tag
+        for j in range(2):
+            for k in range(M):
+                d = np.linalg.norm(X[j, k] - ref[0][j, k])
+                r1 = O.true_residual(Hc, z[k], X[j, k], Bn[j])
+                r2 = O.true_residual(Hc, z[k], ref[0][j, k], Bn[j])
+                assert d <= (r1 + r2) * np.linalg.norm(Bn[j]) / z[k].imag * (1 + 1e-6), (tag, j, k)
+
+    Xst, rst, _, _ = S.shifted_cocg_solve(H, z, B, tol=1e-9, max_iter=4000, block=48, update_form="step")
+    close(Xst.cpu().numpy(), rst, "step")
+    for tb in (24, 32, 40):
+        X, rep, _, rc = S.shifted_cocg_solve(H, z, B, tol=1e-9, max_iter=4000, block=tb, update_form="expanded")
+        assert rc == 0
+        close(X.cpu().numpy(), rep, tb)
+    with pytest.raises(RuntimeError):
+        S.shifted_cocg_solve(H, z, B, fixed_iter=5, block=16, update_form="expanded")
+    with pytest.raises(RuntimeError):
+        S.shifted_cocg_solve(H, z, B, fixed_iter=5, precision="fp32", update_form="expanded")
 
 
 @pytest.mark.parametrize("precision,block", [("fp64", 8), ("fp32", 8), ("fp64", 48)])
@@ -352,7 +410,9 @@ def test_greens_diag_config1_matches_oracle():
     G, repg, _, rc = S.greens_diag(H, p.z, p.rhs_idx, tol=p.tol, max_iter=p.max_iter)
     B = torch.zeros((1, p.H.n), dtype=torch.complex128, device="cuda")
     B[0, 0] = 1
-    X, rep, _, rcx = S.shifted_cocg_solve(H, p.z, B, tol=p.tol, max_iter=p.max_iter, check_true=True)
+    # the step form (which greens_diag's projection mode uses) for the bitwise comparison
+    X, rep, _, rcx = S.shifted_cocg_solve(H, p.z, B, tol=p.tol, max_iter=p.max_iter, check_true=True,
+                                          update_form="step")
     Gg = G.cpu().numpy()[:, 0]
     Xg = X.cpu().numpy()[0]
     assert np.array_equal(Gg, Xg[:, 0])
