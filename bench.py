@@ -737,6 +737,11 @@ def bench_batch(args, S, torch):
         status = np.concatenate(status_l, axis=0)
         iters = np.concatenate(iters_l, axis=0)
         converged += int((status == 0).sum())
+        ok_it = iters[status == 0]
+        if ok_it.size:
+            print(f"[bench] step {st}: iterations of converged pairs: median {int(np.median(ok_it))}, 90 % "
+                  f"{int(np.percentile(ok_it, 90))}, 99 % {int(np.percentile(ok_it, 99))}, max {int(ok_it.max())}; "
+                  f"unconverged {int((status != 0).sum())}", file=sys.stderr, flush=True)
         print(f"[bench] step {st}: {time.perf_counter() - ts:.2f} s rc={max(rcs)} converged "
               f"{int((status == 0).sum())}/{K * M}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
