@@ -44,10 +44,27 @@ def test_measured_traffic_applies_only_to_its_configuration():
 
 
 def test_hot_path_bytes():
+    """The modelled hot path is labelled a model, carries no roofline bound of its own, and counts
+    the update's bytes, 8 vectors per seed iteration and the matrix once per sweep."""
     h = bench.hot_path(1e9, 10, 1000, 2.0, matrix_bytes=12e3, sweeps=10)
     assert h["bytes"] == 1e9 + 10 * 8 * 16 * 1000 + 12e3 * 10
-    assert h["achieved"] == pytest.approx(h["bytes"] / 1e9 / 2.0)
-    assert h["bound"] == "hbm" and h["peak"] == bench.HBM_PEAK_GBS
+    assert h["achieved_gbs"] == pytest.approx(h["bytes"] / 1e9 / 2.0)
+    assert "bound" not in h and "model" in h
+
+
+def test_measured_hot_path_applies_only_to_current_sources_and_workload():
+    path = os.path.join(ROOT, "profiles", "hot_path_diamond_traffic.json")
+    if not os.path.exists(path):
+        assert bench.measured_hot_path("diamond", "anything") is None
+        return
+    with open(path) as f:
+        rec = json.load(f)
+    got = bench.measured_hot_path("diamond", rec["workload"])
+    if rec["library_sources_sha1"] == bench.library_digest():
+        assert got is not None and got["hbm_bytes_per_step"] == rec["hbm_bytes_per_step"]
+        assert bench.measured_hot_path("diamond", rec["workload"] + ", other") is None
+    else:
+        assert got is None
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():

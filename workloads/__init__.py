@@ -18,6 +18,7 @@ from .configs import (
     config1_cubic,
     config2_diamond,
     config3_hubbard,
+    config3_hubbard_rhs,
     config4_diamond_small,
     config5_batch,
     random_sparse_symmetric,
@@ -34,6 +35,7 @@ __all__ = [
     "config1_cubic",
     "config2_diamond",
     "config3_hubbard",
+    "config3_hubbard_rhs",
     "config4_diamond_small",
     "config5_batch",
     "random_sparse_symmetric",
