@@ -670,6 +670,48 @@ int solve(SolveRequest &rq, hipStream_t st)
         if (dj.hub_Dd > HUB_LDS_MAX || dj.n / dj.hub_Dd > (dj.n + 255) / 256) s.hub_lds = 0;
         s.hub_du_max = std::max<int64_t>(s.hub_du_max, dj.n / dj.hub_Dd);
     }
+    // Work lists for a batch of right-hand sides with different row counts: each per-iteration
+    // launch (p update, SpMV, residual update) and the deferred update then covers exactly the
+    // row blocks that exist, not the rectangle of the largest row count times every rhs.  The
+    // items are in the order the rectangle would visit them, so every kernel does the same work
+    // per item and the results are the same bits.
+    std::vector<int2> h_items;
+    int64_t n_grp = 0, n_rhs_items = 0, n_upd = 0;
+    bool uneven = false;
+    for (int64_t j = 0; j < K; ++j) uneven = uneven || hdesc[j].n != n;
+    if (uneven) {
+        auto blocks = [&](int64_t j, int64_t rows_per) { return (hdesc[j].n + rows_per - 1) / rows_per; };
+        const int RB = s.spmv_rb;
+        const int64_t Gn = (K + RB - 1) / RB;
+        if (Gn < 8) {
+            for (int64_t g = 0; g < Gn; ++g)
+                for (int64_t t = 0; t < blocks(g * RB, 256); ++t) h_items.push_back(make_int2((int)g, (int)t));
+        } else {
+            // sets of 8 groups, item 8 t + x of a set on XCD x (the round-robin of workgroups over
+            // the 8 XCDs keeps one group's vectors in one L2); a group shorter than its set's longest
+            // leaves fillers (-1) that exit at once
+            for (int64_t s8 = 0; s8 < (Gn + 7) / 8; ++s8) {
+                int64_t nb = 0;
+                for (int64_t x = 0; x < 8 && 8 * s8 + x < Gn; ++x) nb = std::max(nb, blocks((8 * s8 + x) * RB, 256));
+                for (int64_t t = 0; t < nb; ++t)
+                    for (int64_t x = 0; x < 8; ++x) {
+                        const int64_t g = 8 * s8 + x;
+                        const bool has = g < Gn && t < blocks(g * RB, 256);
+                        h_items.push_back(make_int2(has ? (int)g : -1, (int)t));
+                    }
+            }
+        }
+        n_grp = (int64_t)h_items.size();
+        for (int64_t j = 0; j < K; ++j)
+            for (int64_t t = 0; t < blocks(j, 256); ++t) h_items.push_back(make_int2((int)j, (int)t));
+        n_rhs_items = (int64_t)h_items.size() - n_grp;
+        const int64_t tile = TB >= 24 ? 64 : 256;  // rows per workgroup of the update kernel
+        const int64_t ngr = (Mst + G - 1) / G;
+        for (int64_t y = 0; y < K * ngr; ++y)
+            for (int64_t t = 0; t < blocks(y / ngr, tile); ++t) h_items.push_back(make_int2((int)y, (int)t));
+        n_upd = (int64_t)h_items.size() - n_grp - n_rhs_items;
+        if ((int64_t)h_items.size() >= (1LL << 31)) return fail(SCOCG_EINVAL, "batch too large for its work lists");
+    }
 
     DevBuf bz, bseed, bring, bp, bq, bX, bP, bXproj, bprow, bpi, bpip, bbk, bres, biters, bpst, bact, bnact, bah, bbh,
         brn, bcoef, bp2, bp1, bcnt, bidx, bsd, bstats, bdesc, bwshift, bwslot, bUproj, bblk;
@@ -777,6 +819,17 @@ int solve(SolveRequest &rq, hipStream_t st)
     s.stats = bstats.as<unsigned long long>();
     s.swlog = bswlog.as<int32_t>();
     s.desc = bdesc.as<RhsDesc>();
+    DevBuf bitems;
+    if (uneven) {
+        ALLOC(bitems, h_items.size() * sizeof(int2));
+        HIPCHK(hipMemcpyAsync(bitems.ptr, h_items.data(), h_items.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+        s.it_grp = bitems.as<int2>();
+        s.n_it_grp = n_grp;
+        s.it_rhs = bitems.as<int2>() + n_grp;
+        s.n_it_rhs = n_rhs_items;
+        s.it_upd = bitems.as<int2>() + n_grp + n_rhs_items;
+        s.n_it_upd = n_upd;
+    }
 
     HIPCHK(hipMemcpyAsync(bdesc.ptr, hdesc.data(), K * sizeof(RhsDesc), hipMemcpyHostToDevice, st));
     if (Mst < M) {

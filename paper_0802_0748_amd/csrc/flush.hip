@@ -62,15 +62,17 @@ __global__ void __launch_bounds__(WG) k_flush(const int32_t *__restrict__ blk, c
                                               const int64_t *__restrict__ proj_row,
                                               const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
                                               int ngroups, const int32_t *__restrict__ wshift, int64_t Mst,
-                                              int R)
+                                              int R, const int2 *__restrict__ items)
 {
     // Row blocks run fastest in dispatch order, so the concurrently running workgroups of one
     // shift group stream long contiguous stretches of each pair's x and u.  (Dealing the shift
     // groups of one row block to one XCD instead, to reuse the residual history from L2, made
-    // the launch slower: the x, u accesses then scatter over many DRAM pages.)
-    const int64_t j = blockIdx.y / ngroups;
-    const int g = blockIdx.y % ngroups;
-    const int64_t rb = blockIdx.x;
+    // the launch slower: the x, u accesses then scatter over many DRAM pages.)  An uneven batch
+    // passes its work list (rhs * ngroups + group, row block) in the same order.
+    const int64_t y = items ? items[blockIdx.x].x : blockIdx.y;
+    const int64_t j = y / ngroups;
+    const int g = y % ngroups;
+    const int64_t rb = items ? items[blockIdx.x].y : blockIdx.x;
     // this block's steps, ring slot of its first residual, first block (x, u start at 0)
     const int ns = blk[4 * j + 0];
     if (ns == 0) return;
@@ -238,18 +240,20 @@ __global__ void __launch_bounds__(64 * FL_W)
     k_flush_lds(const int32_t *__restrict__ blk, const double2 *__restrict__ ring, const V *__restrict__ coef,
                 const int32_t *__restrict__ nact, V *__restrict__ X, V *__restrict__ P, double2 *__restrict__ Xproj,
                 const int64_t *__restrict__ proj_row, const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G,
-                int ngroups, const int32_t *__restrict__ wshift, int64_t Mst, int R)
+                int ngroups, const int32_t *__restrict__ wshift, int64_t Mst, int R, const int2 *__restrict__ items)
 {
     static_assert(TB % C == 0, "the block length must be a whole number of chunks");
-    const int64_t j = blockIdx.y / ngroups;
-    const int g = blockIdx.y % ngroups;
+    const int64_t y = items ? items[blockIdx.x].x : blockIdx.y;
+    const int64_t j = y / ngroups;
+    const int g = y % ngroups;
+    const int64_t tile = items ? items[blockIdx.x].y : blockIdx.x;
     const int ns = blk[4 * j + 0];
     if (ns == 0) return;
     const int base = blk[4 * j + 1];
     const bool fresh = blk[4 * j + 2] != 0;
     const int64_t n = desc[j].n;
     const int64_t voff = desc[j].voff;
-    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    const int64_t row0 = tile * 64;
     if (row0 >= n) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x % 64;
@@ -371,20 +375,22 @@ template <int TB>
 __global__ void __launch_bounds__(64 * FL_W)
     k_flush_mfma(const int32_t *__restrict__ blk, const double2 *__restrict__ ring, const double *__restrict__ coefx,
                  const int32_t *__restrict__ nact, double2 *__restrict__ X, double2 *__restrict__ P,
-                 const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G, int ngroups, int R)
+                 const RhsDesc *__restrict__ desc, int64_t ntot, int64_t M, int G, int ngroups, int R,
+                 int64_t KM, const int2 *__restrict__ items)
 {
     static_assert(TB % 4 == 0 && FL_W == 8, "four steps per MFMA, eight waves");
     constexpr int KS = TB / 4;
-    const int64_t KM = M * (int64_t)(gridDim.y / ngroups);  // pairs of the solve (weights are pair-fastest)
-    const int64_t j = blockIdx.y / ngroups;
-    const int g = blockIdx.y % ngroups;
+    const int64_t y = items ? items[blockIdx.x].x : blockIdx.y;
+    const int64_t j = y / ngroups;
+    const int g = y % ngroups;
+    const int64_t tile = items ? items[blockIdx.x].y : blockIdx.x;
     const int ns = blk[4 * j + 0];
     if (ns == 0) return;
     const int base = blk[4 * j + 1];
     const bool fresh = blk[4 * j + 2] != 0;
     const int64_t n = desc[j].n;
     const int64_t voff = desc[j].voff;
-    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    const int64_t row0 = tile * 64;
     if (row0 >= n) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x % 64;
@@ -467,9 +473,9 @@ static hipError_t flush_mfma(const SolveDev &s, hipStream_t st)
         return hipErrorInvalidConfiguration;
     const int ng = (int)((s.M + G - 1) / G);
     if (s.K * ng > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const dim3 g((unsigned)(s.nblk * (WG / 64)), (unsigned)(s.K * ng));
+    const dim3 g = s.it_upd ? dim3((unsigned)s.n_it_upd) : dim3((unsigned)(s.nblk * (WG / 64)), (unsigned)(s.K * ng));
     hipLaunchKernelGGL((k_flush_mfma<TB>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, (const double *)s.coefx, s.nact,
-                       (double2 *)s.X, (double2 *)s.P, s.desc, s.ntot, s.M, G, ng, s.R);
+                       (double2 *)s.X, (double2 *)s.P, s.desc, s.ntot, s.M, G, ng, s.R, s.K * s.M, s.it_upd);
     return hipGetLastError();
 }
 
@@ -480,16 +486,16 @@ static hipError_t flush_lds(const SolveDev &s, hipStream_t st)
     if (G < 1 || G > 64) return hipErrorInvalidConfiguration;
     const int ng = (int)((s.Mst + G - 1) / G);
     if (s.K * ng > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const dim3 g((unsigned)(s.nblk * (WG / 64)), (unsigned)(s.K * ng));
+    const dim3 g = s.it_upd ? dim3((unsigned)s.n_it_upd) : dim3((unsigned)(s.nblk * (WG / 64)), (unsigned)(s.K * ng));
     const V *coef = (const V *)s.coef;
     if (s.Xproj)
         hipLaunchKernelGGL((k_flush_lds<TB, C, NPW, V, true>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
                            (V *)nullptr, (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst,
-                           s.R);
+                           s.R, s.it_upd);
     else
         hipLaunchKernelGGL((k_flush_lds<TB, C, NPW, V, false>), g, dim3(64 * FL_W), 0, st, s.blk, s.ring, coef, s.nact,
                            (V *)s.X, (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng,
-                           (const int32_t *)nullptr, s.M, s.R);
+                           (const int32_t *)nullptr, s.M, s.R, s.it_upd);
     return hipGetLastError();
 }
 
@@ -506,15 +512,15 @@ static hipError_t flush_v(const SolveDev &s, hipStream_t st)
     const int G = s.shifts_per_wg;
     const int ng = (int)((s.Mst + G - 1) / G);
     if (s.K * ng > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const dim3 g((unsigned)s.nblk, (unsigned)(s.K * ng));
+    const dim3 g = s.it_upd ? dim3((unsigned)s.n_it_upd) : dim3((unsigned)s.nblk, (unsigned)(s.K * ng));
     const V *coef = (const V *)s.coef;
     if (s.Xproj)
         hipLaunchKernelGGL((k_flush<TB, V, NP, true>), g, dim3(WG), 0, st, s.blk, s.ring, coef, s.nact, (V *)nullptr,
-                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst, s.R);
+                           (V *)s.P, s.Xproj, s.proj_row, s.desc, s.ntot, s.M, G, ng, s.wshift, s.Mst, s.R, s.it_upd);
     else
         hipLaunchKernelGGL((k_flush<TB, V, NP, false>), g, dim3(WG), 0, st, s.blk, s.ring, coef, s.nact, (V *)s.X,
                            (V *)s.P, (double2 *)nullptr, (const int64_t *)nullptr, s.desc, s.ntot, s.M, G, ng,
-                           (const int32_t *)nullptr, s.M, s.R);
+                           (const int32_t *)nullptr, s.M, s.R, s.it_upd);
     return hipGetLastError();
 }
 

@@ -249,7 +249,14 @@ __global__ void __launch_bounds__(WG) k_init_pairs(SolveDev s)
 template <int RB>
 __global__ void __launch_bounds__(WG) k_pupd(SolveDev s)
 {
-    const int64_t j0 = (int64_t)blockIdx.y * RB;
+    int64_t gq = blockIdx.y, rbq = blockIdx.x;
+    if (s.it_grp) {
+        const int2 it = s.it_grp[blockIdx.x];
+        if (it.x < 0) return;  // filler of an XCD set
+        gq = it.x;
+        rbq = it.y;
+    }
+    const int64_t j0 = gq * RB;
     SeedState st[RB];
     bool run[RB];
     bool any = false;
@@ -264,11 +271,11 @@ __global__ void __launch_bounds__(WG) k_pupd(SolveDev s)
     }
     if (!any) return;
     const RhsDesc d = s.desc[j0];
-    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t row = rbq * WG + threadIdx.x;
     if (s.wproj) {
         // vector projection: also the partials of s_n = w . r_n (bilinear), one per 256 rows
         __shared__ double2 sh2[WG];
-        if ((int64_t)blockIdx.x * WG >= d.n) return;  // uniform: past this rhs's rows
+        if (rbq * WG >= d.n) return;  // uniform: past this rhs's rows
         double2 wr[RB];
         if (row < d.n) {
             double2 *p = s.p + p_index(s, j0, d, row);
@@ -290,7 +297,7 @@ __global__ void __launch_bounds__(WG) k_pupd(SolveDev s)
         for (int b = 0; b < RB; ++b) {
             if (!run[b]) continue;  // uniform across the workgroup
             const double2 v = block_sum2(wr[b], sh2);
-            if (threadIdx.x == 0) s.part3[(j0 + b) * s.nblk + blockIdx.x] = v;
+            if (threadIdx.x == 0) s.part3[(j0 + b) * s.nblk + rbq] = v;
         }
         return;
     }
@@ -581,7 +588,14 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
 {
     __shared__ double2 sh2[WG];
     int64_t g, rb;
-    if (!xcd_group_block(s.nblk, (s.K + RB - 1) / RB, g, rb)) return;
+    if (s.it_grp) {
+        const int2 it = s.it_grp[blockIdx.x];
+        if (it.x < 0) return;  // filler of an XCD set
+        g = it.x;
+        rb = it.y;
+    } else if (!xcd_group_block(s.nblk, (s.K + RB - 1) / RB, g, rb)) {
+        return;
+    }
     const int64_t j0 = g * RB;
     bool run[RB];
     SeedState st[RB];
@@ -691,12 +705,17 @@ __global__ void __launch_bounds__(WG) k_rupd(SolveDev s)
 {
     __shared__ double2 sh2[WG];
     __shared__ double sh1[WG];
-    const int64_t j = blockIdx.y;
+    int64_t j = blockIdx.y, rb = blockIdx.x;
+    if (s.it_rhs) {
+        const int2 it = s.it_rhs[blockIdx.x];
+        j = it.x;
+        rb = it.y;
+    }
     const SeedState st = s.seed[j];
     if (!seed_running(st, s.TB)) return;
     const RhsDesc d = s.desc[j];
-    if ((int64_t)blockIdx.x * WG >= d.n) return;  // past this right-hand side's rows
-    const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (rb * WG >= d.n) return;  // past this right-hand side's rows
+    const int64_t row = rb * WG + threadIdx.x;
     const int slot = (st.base + st.step) % s.R;
     const int nslot = (slot + 1) % s.R;
     const double2 a = s.ahist[j * s.TB + st.step];
@@ -713,8 +732,8 @@ __global__ void __launch_bounds__(WG) k_rupd(SolveDev s)
     rr = block_sum2(rr, sh2);
     nn = block_sum1(nn, sh1);
     if (threadIdx.x == 0) {
-        s.part2[j * s.nblk + blockIdx.x] = rr;
-        s.part1[j * s.nblk + blockIdx.x] = nn;
+        s.part2[j * s.nblk + rb] = rr;
+        s.part1[j * s.nblk + rb] = nn;
     }
 }
 
@@ -1454,9 +1473,10 @@ hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
 {
     const int RB = s.spmv_rb;
     const int64_t G = (s.K + RB - 1) / RB;
-    if (RB == 2) hipLaunchKernelGGL(k_pupd<2>, grid2(s.nblk, G), dim3(WG), 0, st, s);
-    else hipLaunchKernelGGL(k_pupd<1>, grid2(s.nblk, G), dim3(WG), 0, st, s);
-    const int64_t nwg = G < 8 ? s.nblk * G : s.nblk * 8 * ((G + 7) / 8);
+    const dim3 gp = s.it_grp ? dim3((unsigned)s.n_it_grp) : grid2(s.nblk, G);
+    if (RB == 2) hipLaunchKernelGGL(k_pupd<2>, gp, dim3(WG), 0, st, s);
+    else hipLaunchKernelGGL(k_pupd<1>, gp, dim3(WG), 0, st, s);
+    const int64_t nwg = s.it_grp ? s.n_it_grp : (G < 8 ? s.nblk * G : s.nblk * 8 * ((G + 7) / 8));
     if (s.has_sell) {
         if (RB == 2) hipLaunchKernelGGL((k_spmv<2, false>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
         else hipLaunchKernelGGL((k_spmv<1, false>), dim3((unsigned)nwg), dim3(WG), 0, st, s);
@@ -1469,7 +1489,7 @@ hipError_t launch_seed_iteration(const SolveDev &s, hipStream_t st)
     }
     if (s.has_red_small) hipLaunchKernelGGL(k_alpha<WG>, dim3((unsigned)s.K), dim3(WG), 0, st, s);
     if (s.has_red_big) hipLaunchKernelGGL(k_alpha<RWG_BIG>, dim3((unsigned)s.K), dim3(RWG_BIG), 0, st, s);
-    hipLaunchKernelGGL(k_rupd, grid2(s.nblk, s.K), dim3(WG), 0, st, s);
+    hipLaunchKernelGGL(k_rupd, s.it_rhs ? dim3((unsigned)s.n_it_rhs) : grid2(s.nblk, s.K), dim3(WG), 0, st, s);
     if (s.has_red_small) hipLaunchKernelGGL(k_beta<WG>, dim3((unsigned)s.K), dim3(WG), 0, st, s);
     if (s.has_red_big) hipLaunchKernelGGL(k_beta<RWG_BIG>, dim3((unsigned)s.K), dim3(RWG_BIG), 0, st, s);
     return hipGetLastError();

@@ -183,6 +183,16 @@ struct SolveDev {
     int64_t hub_du_max;        // largest number of up-spin configurations among them
     unsigned long long *stats; // [0] algorithmic bytes of the deferred update, [1] updated pairs,
                                // [2] its algorithmic flops
+    // Work lists of batches whose right-hand sides have different row counts (null otherwise): a
+    // launch then covers exactly the (group or rhs, row block) items that hold rows, instead of
+    // the full rectangle of largest-row-count x right-hand sides with most workgroups exiting.
+    const int2 *it_grp;        // [n_it_grp] (rhs group of spmv_rb, 256-row block), in XCD sets of 8 groups
+                               // (item 8 t + x of a set is group 8 s + x, block t); x = -1 marks a filler
+    int64_t n_it_grp;
+    const int2 *it_rhs;        // [n_it_rhs] (rhs, 256-row block)
+    int64_t n_it_rhs;
+    const int2 *it_upd;        // [n_it_upd] (rhs * shift groups + group, row tile of the update kernel)
+    int64_t n_it_upd;
     int32_t *swlog;            // [K][M][2] seed switches of each rhs: (iterations done, new seed shift);
                                // a shift becomes the seed at most once, so M entries suffice
 };
