@@ -108,7 +108,8 @@ def _values(model, disp):
 
 def test_band_energy_forces_match_finite_differences():
     """Forces -dE/dR through t(r) = exp(-2 (r - r0)) on the 32-atom cell, against central
-    differences (h = 1e-5) of the GPU band energy with the contour held fixed."""
+    differences (h = 1e-5) of the GPU band energy with the contour held fixed (5 coordinates), and
+    of the dense CPU evaluation of the same quadrature energy (all 96 coordinates)."""
     S = _S()
     from paper_0802_0748_amd.autograd import band_energy
 
@@ -131,6 +132,27 @@ def test_band_energy_forces_match_finite_differences():
             Es.append(band_energy(_values(model, d), H, z, w, tol=1e-13, max_iter=5000).item())
         fd = -(Es[0] - Es[1]) / (2 * h)
         assert abs(fd - forces[a, c]) < 1e-6 * max(1.0, abs(forces[a, c])), (a, c, fd, forces[a, c])
+    # all 96 coordinates: central differences of the same quadrature energy evaluated densely on
+    # the CPU, E = Re sum_k w_k z_k sum_i 1/(z_k - lambda_i) over the eigenvalues of H(R)
+    rows = np.repeat(np.arange(Hc.n), np.diff(Hc.row_ptr))
+    zz, ww = np.asarray(z), np.asarray(w)
+
+    def e_dense(d):
+        A = np.zeros((Hc.n, Hc.n))
+        A[rows, Hc.col] = _values(model, d).numpy()
+        lam = np.linalg.eigvalsh(A)
+        return float(np.real(np.sum(ww * zz * np.sum(1.0 / (zz[:, None] - lam[None, :]), axis=1))))
+
+    assert abs(e_dense(disp0) - E.item()) < 1e-10 * max(1.0, abs(E.item()))
+    fd_all = np.zeros_like(forces)
+    for a in range(forces.shape[0]):
+        for c in range(3):
+            dp, dm = disp0.clone(), disp0.clone()
+            dp[a, c] += h
+            dm[a, c] -= h
+            fd_all[a, c] = -(e_dense(dp) - e_dense(dm)) / (2 * h)
+    assert forces.shape == (32, 3)
+    assert np.max(np.abs(fd_all - forces)) < 1e-6 * max(1.0, np.max(np.abs(forces))), np.max(np.abs(fd_all - forces))
 
 
 def test_band_energy_gradient_matches_dense_autograd():
