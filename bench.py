@@ -137,6 +137,35 @@ def measured_hot_path(workload, config):
     return rec
 
 
+def measured_kernels(workload, config):
+    """Per-kernel rates of the hot path from the committed rocprofv3 summaries of the current
+    library sources on this workload: the average duration of each kernel in the benchmark's
+    own (overlapped) schedule from the kernel trace, its memory-side bytes per launch from the
+    FETCH_SIZE / WRITE_SIZE summary, and the ratio.  None if either summary is missing or stale."""
+    recs = []
+    for name in (f"kernels_{workload}_stats.json", f"hot_path_{workload}_traffic.json"):
+        try:
+            with open(os.path.join(ROOT, "profiles", name)) as f:
+                recs.append(json.load(f))
+        except (OSError, ValueError):
+            return None
+    trace, traffic = recs
+    digest = library_digest()
+    if any(r.get("library_sources_sha1") != digest or r.get("workload") != config for r in recs):
+        return None
+    avg = {k["kernel"]: k["avg_us"] for k in trace["kernels"]}
+    out = []
+    for k in traffic["kernels"]:
+        if k["kernel"] not in avg or k["dispatches"] < 100:
+            continue
+        per = (k["read_bytes"] + k["write_bytes"]) / k["dispatches"]
+        gbs = per / 1e3 / avg[k["kernel"]]
+        out.append({"kernel": k["kernel"].replace("HIP_vector_type<double, 2u>", "double2"),
+                    "avg_us": avg[k["kernel"]], "memory_side_bytes_per_launch": per, "achieved_gbs": gbs,
+                    "frac_of_peak": gbs / HBM_PEAK_GBS})
+    return out
+
+
 def measured_traffic(workload, config=None, precision="fp64"):
     """HBM bytes per launch of the update kernel from the committed rocprofv3 counter
     summary, if it was taken on this workload, configuration and storage precision (the
@@ -412,6 +441,13 @@ def trace_summary(args):
                       f"{100 * line['roofline']['frac']:.1f} % of the {line['roofline']['bound']} peak)."]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
+    # the same rows as data, tied to the library sources, for the benchmark's per-kernel record
+    rec = {"workload": line["config"]["workload"], "library_sources_sha1": library_digest(), "command": command,
+           "kernels": [{"kernel": r["Name"].split("(")[0].replace("void ", ""), "calls": int(r["Calls"]),
+                        "total_ms": float(r["TotalDurationNs"]) / 1e6, "avg_us": float(r["AverageNs"]) / 1e3}
+                       for r in rows]}
+    with open(out.replace(".md", ".json"), "w") as f:
+        json.dump(rec, f, indent=1)
     print(f"[bench] wrote {out}", file=sys.stderr)
     return 0
 
@@ -1223,6 +1259,13 @@ def main():
                                      "hbm_bytes_per_step": rec["hbm_bytes_per_step"],
                                      "source": f"profiles/hot_path_{args.workload}_traffic.md (FETCH_SIZE + WRITE_SIZE "
                                                "over every kernel of one solve)"}
+    kern = measured_kernels(args.workload, wl_desc)
+    if kern is not None:
+        # the SpMV and the other kernels of the path, each against the HBM peak (memory side of L2:
+        # Infinity Cache hits included), from the committed trace and counter summaries
+        line["kernels_measured"] = {"source": f"profiles/kernels_{args.workload}_stats.json (rocprofv3 kernel trace) "
+                                              f"and profiles/hot_path_{args.workload}_traffic.json (FETCH_SIZE + "
+                                              "WRITE_SIZE)", "peak_gbs": HBM_PEAK_GBS, "kernels": kern}
     if line["roofline"]["bound"] == "hbm":
         line["roofline"]["frac_of_copy"] = line["roofline"]["achieved"] / copy_gbs
     else:

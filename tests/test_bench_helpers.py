@@ -67,6 +67,27 @@ def test_measured_hot_path_applies_only_to_current_sources_and_workload():
         assert got is None
 
 
+def test_measured_kernels_apply_only_to_current_sources_and_workload():
+    """The per-kernel record (trace durations with counter bytes) is reported only while both
+    committed summaries were taken on the current library sources and this workload."""
+    paths = [os.path.join(ROOT, "profiles", n) for n in ("kernels_diamond_stats.json", "hot_path_diamond_traffic.json")]
+    if not all(os.path.exists(p) for p in paths):
+        assert bench.measured_kernels("diamond", "anything") is None
+        return
+    recs = []
+    for p in paths:
+        with open(p) as f:
+            recs.append(json.load(f))
+    got = bench.measured_kernels("diamond", recs[0]["workload"])
+    if all(r["library_sources_sha1"] == bench.library_digest() for r in recs) and recs[0]["workload"] == recs[1]["workload"]:
+        assert got and any("k_spmv" in k["kernel"] for k in got)
+        for k in got:
+            assert k["achieved_gbs"] == pytest.approx(k["memory_side_bytes_per_launch"] / 1e3 / k["avg_us"])
+        assert bench.measured_kernels("diamond", recs[0]["workload"] + ", other") is None
+    else:
+        assert got is None
+
+
 def test_more_than_one_gpu_is_refused_with_a_message():
     import subprocess
 
