@@ -1076,6 +1076,38 @@ def hubbard_matrix_free_record(S, torch, steps=1):
             "roofline": update_roofline(upd[0], upd[1], upd[2], upd[3], "hubbard_matrix_free", "fp64", desc)}
 
 
+def cubic_record(S, torch, steps=3):
+    """The small latency-bound workload: G_00(z_k) of the 16^3 simple-cubic lattice (on-site
+    U[-1, 1], hopping -1), 64 shifts eps in [-7, 7] with eta = 0.01, tol 1e-10, projection mode;
+    a third workload measured in the same run."""
+    from workloads import config1_cubic
+
+    p = config1_cubic()
+    p.max_iter = 20000  # 1e-10 takes about 10,650 iterations, more than the stated 3,000
+    H = S.Hamiltonian.from_csr(p.H)
+    S.greens_diag(H, p.z[:4], p.rhs_idx, fixed_iter=32)  # code paths (not timed)
+
+    def timed(tol):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        conv = 0
+        for _ in range(steps):
+            _, rep, _, rc = S.greens_diag(H, p.z, p.rhs_idx, tol=tol, max_iter=p.max_iter)
+            conv += int((rep["status"] == 0).sum())
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return conv, el, int(rep["iters"].max())
+
+    conv, el, it = timed(p.tol)
+    conv8, el8, it8 = timed(1e-8)
+    desc = f"simple cubic 16^3 (n={p.H.n}), 64 shifts eta=0.01, G_00, tol 1e-10, max_iter {p.max_iter}"
+    return {"metric": METRIC, "value": conv / el, "unit": "solves/s", "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "converged": conv, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": desc, "n": p.H.n, "n_shift": len(p.z), "n_rhs": 1, "iterations_per_step": it},
+            "at_tol_1e-8": {"value": conv8 / el8, "ms_per_step": 1e3 * el8 / steps, "converged": conv8,
+                            "iterations_per_step": it8}}
+
+
 def run_variants(S, torch, n_rhs):
     """The diamond problem with n_rhs right-hand sides solved by several forms of the solver."""
     from workloads import config2_diamond
@@ -1282,7 +1314,8 @@ def main():
         print(f"[bench] plain single-rhs path: {line['plain_single_rhs']['seconds']:.2f} s for one rhs, batched speedup "
               f"{line['plain_single_rhs']['speedup_of_value']:.1f}", file=sys.stderr, flush=True)
         del X
-        line["extra_workloads"] = {"hubbard_matrix_free": hubbard_matrix_free_record(S, torch)}
+        line["extra_workloads"] = {"hubbard_matrix_free": hubbard_matrix_free_record(S, torch),
+                                   "cubic": cubic_record(S, torch)}
         print(f"[bench] matrix-free Hubbard: {line['extra_workloads']['hubbard_matrix_free']['ms_per_step'] / 1e3:.2f} s "
               "per solve", file=sys.stderr, flush=True)
     if args.variants:
