@@ -170,8 +170,9 @@ int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, 
                 const scocg_opts *o, double *G, scocg_pair_report *rep, scocg_tape_t *tape, void *stream);
 
 /*
- * greens_diag for callers that cannot allocate device memory: code that runs under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels and
+ * greens_diag for callers that cannot allocate device memory: tight serving loops, harnesses
+ * that forbid hipMalloc, programs that keep their device allocations fixed around HIP graph
+ * capture (the call itself waits on the stream, so it is made outside a capture).  Same arguments, kernels and
  * results (bit for bit) as greens_diag without a tape; every work buffer of the solve lives in
  * one device array of SCOCG_NOALLOC_MAX_BYTES that the library holds on each device it runs on
  * until the process ends.  The call allocates no device or pinned memory and creates no
@@ -184,7 +185,8 @@ int greens_diag(scocg_csr_t H, int64_t n_shift, const double *z, int64_t n_rhs, 
  *   scocg_last_error(), before any work.
  *   The array keeps the last call's contents; each call initialises what it reads.  Calls on one
  *   device share its array, so they are serialised by a lock in the library: a second call on the
- *   same device (another host thread) waits until the first has finished.
+ *   same device (another host thread) waits until the first has finished, its GPU work included
+ *   (also when the first returns an error).
  * Synchronous on stream.  Errors as greens_diag.
  */
 #define SCOCG_NOALLOC_MAX_BYTES (128ull << 20)

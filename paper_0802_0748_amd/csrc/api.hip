@@ -1751,6 +1751,12 @@ extern "C" int greens_diag_noalloc(scocg_csr_t H, int64_t n_shift, const double 
     }
     carve((char *)g_scratch_ptr[dev], L);
     hipStream_t st = (hipStream_t)stream;
+    // the lock is released only after the stream has drained, on every return path, so no kernel
+    // of this call still uses the array when the next call on this device starts
+    struct DrainOnExit {
+        hipStream_t st;
+        ~DrainOnExit() { (void)hipStreamSynchronize(st); }
+    } drain{st};
     const auto t_start = std::chrono::steady_clock::now();
     g_timing = scocg_timing{};
 
