@@ -575,6 +575,7 @@ __global__ void __launch_bounds__(HUB_WG) k_spmv_hub_lds(SolveDev s)
 // Slots of a slice processed per batch: the column and value loads of SPMV_CHUNK slots are
 // issued together, then their gathers, so each wave has many loads in flight.
 static constexpr int SPMV_CHUNK = 8;
+static constexpr int SPMV_TAIL = 4;
 
 // q = (z_s 1 - H) p for RB right-hand sides that share one matrix (consecutive rhs j0 .. j0+RB-1):
 // the column and value of each slot are loaded once and serve all RB gathers.  The products
@@ -655,15 +656,34 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
                     ay[b] = fma(v[u], pc[u][b].y, ay[b]);
                 }
         }
-        for (; k < w; ++k) {
-            const int c = colp[(int64_t)k * 64];
-            const double v = valp[(int64_t)k * 64];
+        // the last w - k (< SPMV_CHUNK) slots, SPMV_TAIL at a time: their loads are also issued
+        // together (the count is the same for the whole wave), then added in slot order
+        for (; k < w; k += SPMV_TAIL) {
+            const int rem = w - k;
+            int c[SPMV_TAIL];
+            double v[SPMV_TAIL];
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
-                const double2 pc = pv[(int64_t)RB * c + b];
-                ax[b] = fma(v, pc.x, ax[b]);
-                ay[b] = fma(v, pc.y, ay[b]);
+            for (int u = 0; u < SPMV_TAIL; ++u) {
+                c[u] = 0;
+                v[u] = 0.0;
+                if (u < rem) {
+                    c[u] = colp[(int64_t)(k + u) * 64];
+                    v[u] = valp[(int64_t)(k + u) * 64];
+                }
             }
+            double2 pc[SPMV_TAIL][RB];
+#pragma unroll
+            for (int u = 0; u < SPMV_TAIL; ++u)
+#pragma unroll
+                for (int b = 0; b < RB; ++b) pc[u][b] = u < rem ? pv[(int64_t)RB * c[u] + b] : cmk(0, 0);
+#pragma unroll
+            for (int u = 0; u < SPMV_TAIL; ++u)
+                if (u < rem)
+#pragma unroll
+                    for (int b = 0; b < RB; ++b) {
+                        ax[b] = fma(v[u], pc[u][b].x, ax[b]);
+                        ay[b] = fma(v[u], pc[u][b].y, ay[b]);
+                    }
         }
     }
 #pragma unroll
