@@ -20,18 +20,27 @@ namespace scocg {
 // reductions
 // ---------------------------------------------------------------------------------------
 // Tree sums over the NT threads of a workgroup (sh holds NT entries); the result is in
-// every thread.
+// every thread.  Level s adds entry t + s to entry t for t < s; the levels down to s = 64 go
+// through LDS with a barrier each, the last six inside the first wave by lane shuffles (lane t
+// adds lane t + s, the same additions in the same order, without a barrier per level).
 template <int NT = WG>
 __device__ inline double2 block_sum2(double2 v, double2 *sh)
 {
-    int t = threadIdx.x;
+    static_assert(NT >= 128, "the LDS levels end at s = 64");
+    const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s >= 64; s >>= 1) {
         if (t < s) sh[t] = cadd(sh[t], sh[t + s]);
         __syncthreads();
     }
-    double2 r = sh[0];
+    if (t < 64) {
+        double2 x = sh[t];
+        for (int s = 32; s > 0; s >>= 1) x = cadd(x, make_double2(__shfl_down(x.x, s, 64), __shfl_down(x.y, s, 64)));
+        if (t == 0) sh[0] = x;
+    }
+    __syncthreads();
+    const double2 r = sh[0];
     __syncthreads();
     return r;
 }
@@ -39,14 +48,21 @@ __device__ inline double2 block_sum2(double2 v, double2 *sh)
 template <int NT = WG>
 __device__ inline double block_sum1(double v, double *sh)
 {
-    int t = threadIdx.x;
+    static_assert(NT >= 128, "the LDS levels end at s = 64");
+    const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s >= 64; s >>= 1) {
         if (t < s) sh[t] += sh[t + s];
         __syncthreads();
     }
-    double r = sh[0];
+    if (t < 64) {
+        double x = sh[t];
+        for (int s = 32; s > 0; s >>= 1) x += __shfl_down(x, s, 64);
+        if (t == 0) sh[0] = x;
+    }
+    __syncthreads();
+    const double r = sh[0];
     __syncthreads();
     return r;
 }
