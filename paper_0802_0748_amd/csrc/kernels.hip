@@ -67,6 +67,74 @@ __device__ inline double block_sum1(double v, double *sh)
     return r;
 }
 
+// block_sum2 and block_sum1 of two values at once: each has its own tree, the same additions
+// in the same order as alone, with one set of barriers for both.
+template <int NT = WG>
+__device__ inline void block_sum21(double2 &v2, double &v1, double2 *sh2, double *sh1)
+{
+    static_assert(NT >= 128, "the LDS levels end at s = 64");
+    const int t = threadIdx.x;
+    sh2[t] = v2;
+    sh1[t] = v1;
+    __syncthreads();
+    for (int s = NT / 2; s >= 64; s >>= 1) {
+        if (t < s) {
+            sh2[t] = cadd(sh2[t], sh2[t + s]);
+            sh1[t] += sh1[t + s];
+        }
+        __syncthreads();
+    }
+    if (t < 64) {
+        double2 x = sh2[t];
+        double y = sh1[t];
+        for (int s = 32; s > 0; s >>= 1) {
+            x = cadd(x, make_double2(__shfl_down(x.x, s, 64), __shfl_down(x.y, s, 64)));
+            y += __shfl_down(y, s, 64);
+        }
+        if (t == 0) {
+            sh2[0] = x;
+            sh1[0] = y;
+        }
+    }
+    __syncthreads();
+    v2 = sh2[0];
+    v1 = sh1[0];
+    __syncthreads();
+}
+
+// block_sum2 of two values at once (each its own tree, the same additions in the same order).
+template <int NT = WG>
+__device__ inline void block_sum22(double2 &va, double2 &vb, double2 *sha, double2 *shb)
+{
+    static_assert(NT >= 128, "the LDS levels end at s = 64");
+    const int t = threadIdx.x;
+    sha[t] = va;
+    shb[t] = vb;
+    __syncthreads();
+    for (int s = NT / 2; s >= 64; s >>= 1) {
+        if (t < s) {
+            sha[t] = cadd(sha[t], sha[t + s]);
+            shb[t] = cadd(shb[t], shb[t + s]);
+        }
+        __syncthreads();
+    }
+    if (t < 64) {
+        double2 x = sha[t], y = shb[t];
+        for (int s = 32; s > 0; s >>= 1) {
+            x = cadd(x, make_double2(__shfl_down(x.x, s, 64), __shfl_down(x.y, s, 64)));
+            y = cadd(y, make_double2(__shfl_down(y.x, s, 64), __shfl_down(y.y, s, 64)));
+        }
+        if (t == 0) {
+            sha[0] = x;
+            shb[0] = y;
+        }
+    }
+    __syncthreads();
+    va = sha[0];
+    vb = shb[0];
+    __syncthreads();
+}
+
 __device__ inline double load_coherent(const double *p)
 {
     unsigned long long v = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
@@ -139,6 +207,38 @@ __device__ inline double sum_partials1(const double *part, int64_t nblk, double 
     }
     for (; b < nblk; b += NT) acc += COHERENT ? load_coherent(part + b) : part[b];
     return block_sum1<NT>(acc, sh);
+}
+
+// sum_partials2 and sum_partials1 (plain loads) of two partial arrays at once: each thread adds
+// its partials of each array in the same order as alone, then block_sum21.
+template <int NT = WG>
+__device__ inline void sum_partials21(const double2 *part2, const double *part1, int64_t nblk, double2 *sh2,
+                                      double *sh1, double2 &out2, double &out1)
+{
+    double2 acc2 = cmk(0, 0);
+    double acc1 = 0;
+    int64_t b = threadIdx.x;
+    for (; b + (SUM_BATCH - 1) * NT < nblk; b += SUM_BATCH * NT) {
+        double2 v2[SUM_BATCH];
+        double v1[SUM_BATCH];
+#pragma unroll
+        for (int u = 0; u < SUM_BATCH; ++u) {
+            v2[u] = part2[b + u * NT];
+            v1[u] = part1[b + u * NT];
+        }
+#pragma unroll
+        for (int u = 0; u < SUM_BATCH; ++u) {
+            acc2 = cadd(acc2, v2[u]);
+            acc1 += v1[u];
+        }
+    }
+    for (; b < nblk; b += NT) {
+        acc2 = cadd(acc2, part2[b]);
+        acc1 += part1[b];
+    }
+    block_sum21<NT>(acc2, acc1, sh2, sh1);
+    out2 = acc2;
+    out1 = acc1;
 }
 
 // The per-rhs reductions of the seed iteration (alpha, beta) run with WG threads, or with
@@ -604,6 +704,7 @@ template <int RB, bool HUB>
 __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
 {
     __shared__ double2 sh2[WG];
+    __shared__ double2 sh2b[RB > 1 ? WG : 1];
     int64_t g, rb;
     if (s.it_grp) {
         const int2 it = s.it_grp[blockIdx.x];
@@ -702,20 +803,31 @@ __global__ void __launch_bounds__(WG) k_spmv(SolveDev s)
                     }
         }
     }
+    double2 pq[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-        double2 pq = cmk(0, 0);
+        pq[b] = cmk(0, 0);
         if (run[b] && slice < d.nslices && row < d.n) {
             const double2 pr = pv[RB * row + b];
             const double2 qv = cfma(st[b].zs, pr, make_double2(-ax[b], -ay[b]));
             s.q[s.desc[j0 + b].voff + row] = qv;
-            pq = cmul(pr, qv);
-        }
-        if (run[b]) {  // uniform across the workgroup
-            pq = block_sum2(pq, sh2);
-            if (threadIdx.x == 0) s.part2[(j0 + b) * s.nblk + rb] = pq;
+            pq[b] = cmul(pr, qv);
         }
     }
+    // run[] is uniform across the workgroup; both partials of a running pair share the barriers
+    bool both = false;
+    if constexpr (RB == 2) {
+        both = run[0] && run[1];
+        if (both) block_sum22(pq[0], pq[1], sh2, sh2b);
+    }
+    if (!both)
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if (run[b]) pq[b] = block_sum2(pq[b], sh2);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if (run[b]) s.part2[(j0 + b) * s.nblk + rb] = pq[b];
 }
 
 template <int NT>
@@ -765,8 +877,7 @@ __global__ void __launch_bounds__(WG) k_rupd(SolveDev s)
         rr = cmul(rn, rn);
         nn = cabs2(rn);
     }
-    rr = block_sum2(rr, sh2);
-    nn = block_sum1(nn, sh1);
+    block_sum21(rr, nn, sh2, sh1);
     if (threadIdx.x == 0) {
         s.part2[j * s.nblk + rb] = rr;
         s.part1[j * s.nblk + rb] = nn;
@@ -783,8 +894,10 @@ __global__ void __launch_bounds__(NT) k_beta(SolveDev s)
     if (!seed_running(st, s.TB)) return;
     if (red_big(s.desc[j]) != (NT == RWG_BIG)) return;
     const int64_t np = nparts(s.desc[j]);
-    const double2 rho_new = sum_partials2<false, NT>(s.part2 + j * s.nblk, np, sh2);
-    const double rnorm = sqrt(sum_partials1<false, NT>(s.part1 + j * s.nblk, np, sh1));
+    double2 rho_new;
+    double rn2;
+    sum_partials21<NT>(s.part2 + j * s.nblk, s.part1 + j * s.nblk, np, sh2, sh1, rho_new, rn2);
+    const double rnorm = sqrt(rn2);
     if (threadIdx.x == 0) {
         const double2 a = s.ahist[j * s.TB + st.step];
         const double2 beta = cdiv(rho_new, st.rho);
